@@ -1,0 +1,233 @@
+"""Seeded synthetic inputs: jittered Kuhn-cube tetrahedral meshes and nodal velocity fields.
+
+This module only *generates inputs*. It holds none of the assembly arithmetic, so both the
+CPU oracle's tests and the GPU path draw their meshes from here.
+
+The paper evaluates on Alya's benchmark meshes (Table 2: 1.2k to 32.7M elements, about 5.7-5.8
+tetrahedra per node for the Sphere cases). Those meshes are not available, so unit cubes split
+into hexahedra and each hexahedron into six Kuhn tetrahedra stand in for them: a 64^3 cube gives
+1,572,864 tets on 274,625 nodes, a 128^3 cube 12,582,912 tets on 2,146,689 nodes.
+
+Node ids: (i, j, k) -> i + (n+1) * (j + (n+1) * k) before any renumbering.
+Element order: hexes with i fastest, then j, then k; six tets per hex in the axis-permutation
+order (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x). Every tet is positively oriented.
+
+Random draws use ``numpy.random.default_rng(seed)`` in this fixed order:
+jitter (npoin x 3), then node permutation, then velocity noise.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Kuhn split of the unit hex along its (0,0,0)->(1,1,1) diagonal: one tet per permutation
+# of the axes. Vertex path: origin, +e_p0, +e_p1, +e_p2.
+_AXIS_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def _perm_sign(p):
+    s = 1
+    for i in range(3):
+        for j in range(i + 1, 3):
+            if p[i] > p[j]:
+                s = -s
+    return s
+
+
+def _kuhn_corner_table():
+    """(6, 4, 3) int array of hex-corner offsets for each tet, positively oriented."""
+    tab = np.zeros((6, 4, 3), dtype=np.int64)
+    for t, p in enumerate(_AXIS_PERMS):
+        v = np.zeros(3, dtype=np.int64)
+        verts = [v.copy()]
+        for ax in p:
+            v[ax] += 1
+            verts.append(v.copy())
+        if _perm_sign(p) < 0:  # odd permutation: swap two vertices to flip the orientation
+            verts[2], verts[3] = verts[3], verts[2]
+        tab[t] = np.array(verts)
+    return tab
+
+
+@dataclasses.dataclass
+class Mesh:
+    """A linear-tetrahedron mesh with a nodal velocity field (all host NumPy arrays)."""
+    n: int                    # hexes per cube edge
+    lnods: np.ndarray         # int32 [nelem][4], 0-based node ids
+    coord: np.ndarray         # float64 [npoin][3]
+    velocity: np.ndarray      # float64 [npoin][3]
+    rho: float = 1.0
+    mu: float = 1e-3
+    dt: float = 1e-2
+    name: str = ""
+
+    @property
+    def npoin(self) -> int:
+        return int(self.coord.shape[0])
+
+    @property
+    def nelem(self) -> int:
+        return int(self.lnods.shape[0])
+
+
+def cube_counts(n: int):
+    """(npoin, nelem, nedges, nnzb) of the Kuhn-split n^3 cube (closed forms)."""
+    npoin = (n + 1) ** 3
+    nelem = 6 * n ** 3
+    edges = 3 * n * (n + 1) ** 2 + 3 * n ** 2 * (n + 1) + n ** 3
+    return npoin, nelem, edges, npoin + 2 * edges
+
+
+def kuhn_cube(n: int):
+    """Unjittered Kuhn cube: (lnods int32 [6n^3][4], coord float64 [(n+1)^3][3])."""
+    m = n + 1
+    g = np.arange(m, dtype=np.float64) / n
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    coord = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = (i + m * (j + m * k)).ravel().astype(np.int64)           # hex origin node, i fastest
+    tab = _kuhn_corner_table()                                       # (6,4,3)
+    off = tab[..., 0] + m * (tab[..., 1] + m * tab[..., 2])          # (6,4)
+    lnods = (base[:, None, None] + off[None, :, :]).reshape(-1, 4)
+    return lnods.astype(np.int32), coord
+
+
+def taylor_green(coord: np.ndarray) -> np.ndarray:
+    """Smooth vortex (Taylor-Green) velocity at the given points, float64 [npoin][3]."""
+    x, y, z = coord[:, 0], coord[:, 1], coord[:, 2]
+    px, py, pz = math.pi * x, math.pi * y, math.pi * z
+    u = np.sin(px) * np.cos(py) * np.cos(pz)
+    v = -np.cos(px) * np.sin(py) * np.cos(pz)
+    return np.stack([u, v, np.zeros_like(u)], axis=1)
+
+
+def node_graph_rcm(lnods: np.ndarray, npoin: int) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the node graph (SciPy); returns new_id[old_id]."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+
+    ln = lnods.astype(np.int64)
+    rows, cols = [], []
+    for a in range(4):
+        for b in range(a + 1, 4):
+            lo = np.minimum(ln[:, a], ln[:, b])
+            hi = np.maximum(ln[:, a], ln[:, b])
+            rows.append(lo)
+            cols.append(hi)
+    key = np.unique(np.concatenate(rows) * npoin + np.concatenate(cols))
+    lo, hi = key // npoin, key % npoin
+    r = np.concatenate([lo, hi])
+    c = np.concatenate([hi, lo])
+    g = sp.csr_matrix((np.ones(r.size, dtype=np.int8), (r, c)), shape=(npoin, npoin))
+    order = reverse_cuthill_mckee(g, symmetric_mode=True)            # order[k] = old id at slot k
+    new_id = np.empty(npoin, dtype=np.int64)
+    new_id[order] = np.arange(npoin, dtype=np.int64)
+    return new_id
+
+
+def make_mesh(n: int, *, jitter: bool = False, permute: bool = False, rcm: bool = False,
+              sort_elements: bool = False, velocity: str = "uniform", seed: int = 0,
+              rho: float = 1.0, mu: float = 1e-3, dt: float = 1e-2, name: str = "") -> Mesh:
+    """Build a seeded Kuhn-cube mesh.
+
+    jitter        every node coordinate component moves by U[-0.2h, 0.2h], h = 1/n
+                  (keeps every tet positively oriented: the smallest altitude is h/sqrt(2)).
+    permute       random relabelling of the nodes.
+    rcm           after the permutation, renumber by reverse Cuthill-McKee on the node graph.
+    sort_elements stable sort of the elements by their smallest node id.
+    velocity      "uniform": U[-1,1]^3 per node; "vortex": Taylor-Green at the (jittered)
+                  coordinates plus 0.01 * U[-1,1]^3.
+    """
+    rng = np.random.default_rng(seed)
+    lnods, coord = kuhn_cube(n)
+    npoin = coord.shape[0]
+    if jitter:
+        h = 1.0 / n
+        coord = coord + rng.uniform(-0.2 * h, 0.2 * h, size=(npoin, 3))
+    if permute:
+        perm = rng.permutation(npoin)                                # new id of old node
+        new_coord = np.empty_like(coord)
+        new_coord[perm] = coord
+        coord = new_coord
+        lnods = perm[lnods].astype(np.int32)
+    if velocity == "uniform":
+        vel = rng.uniform(-1.0, 1.0, size=(npoin, 3))
+    elif velocity == "vortex":
+        vel = taylor_green(coord) + 0.01 * rng.uniform(-1.0, 1.0, size=(npoin, 3))
+    elif velocity == "zero":
+        vel = np.zeros((npoin, 3))
+    else:
+        raise ValueError(f"unknown velocity field {velocity!r}")
+    if rcm:
+        new_id = node_graph_rcm(lnods, npoin)
+        new_coord = np.empty_like(coord)
+        new_coord[new_id] = coord
+        new_vel = np.empty_like(vel)
+        new_vel[new_id] = vel
+        coord, vel = new_coord, new_vel
+        lnods = new_id[lnods].astype(np.int32)
+    if sort_elements:
+        order = np.argsort(lnods.min(axis=1), kind="stable")
+        lnods = np.ascontiguousarray(lnods[order])
+    return Mesh(n=n, lnods=np.ascontiguousarray(lnods, dtype=np.int32),
+                coord=np.ascontiguousarray(coord, dtype=np.float64),
+                velocity=np.ascontiguousarray(vel, dtype=np.float64),
+                rho=rho, mu=mu, dt=dt, name=name)
+
+
+# ---------------------------------------------------------------------------------------------
+# The workloads. Sizes and value distributions follow the five configurations of the build; the
+# cube meshes stand in for Alya's Sphere/Elbow benchmarks (Table 2 of the paper).
+# ---------------------------------------------------------------------------------------------
+
+def config_small() -> Mesh:
+    """8^3 cube (3,072 tets, 729 nodes), unjittered, identity numbering, U[-1,1]^3 velocity."""
+    return make_mesh(8, velocity="uniform", seed=1, rho=1.0, mu=1e-3, dt=1e-2, name="cube8")
+
+
+def config_64() -> Mesh:
+    """64^3 cube (1,572,864 tets), jittered, random node permutation, elements in generation order."""
+    return make_mesh(64, jitter=True, permute=True, velocity="vortex", seed=2,
+                     rho=1.0, mu=1e-3, dt=5e-3, name="cube64_perm")
+
+
+def config_128() -> Mesh:
+    """128^3 cube (12,582,912 tets), jittered, permuted then RCM-renumbered, elements sorted."""
+    return make_mesh(128, jitter=True, permute=True, rcm=True, sort_elements=True,
+                     velocity="vortex", seed=3, rho=1.0, mu=1e-3, dt=5e-3, name="cube128_rcm")
+
+
+def batch_params(nmesh: int = 64, seed: int = 4, nmin: int = 8, nmax: int = 48):
+    """Per-mesh (n, rho, mu, dt, mesh_seed) for the batched workload."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nmin, nmax + 1, size=nmesh)
+    rho = rng.uniform(0.5, 2.0, size=nmesh)
+    mu = 10.0 ** rng.uniform(-4.0, -2.0, size=nmesh)
+    dt = rng.uniform(1e-3, 1e-2, size=nmesh)
+    seeds = rng.integers(0, 2 ** 31 - 1, size=nmesh)
+    return [dict(n=int(ns[i]), rho=float(rho[i]), mu=float(mu[i]), dt=float(dt[i]),
+                 seed=int(seeds[i])) for i in range(nmesh)]
+
+
+def config_batch(nmesh: int = 64, seed: int = 4, nmin: int = 8, nmax: int = 48):
+    """64 jittered, permuted cubes with n ~ U{8..48}; per-mesh rho, mu, dt as drawn."""
+    out = []
+    for i, p in enumerate(batch_params(nmesh, seed, nmin, nmax)):
+        out.append(make_mesh(p["n"], jitter=True, permute=True, velocity="vortex",
+                             seed=p["seed"], rho=p["rho"], mu=p["mu"], dt=p["dt"],
+                             name=f"batch{i}_n{p['n']}"))
+    return out
+
+
+def served_sizes(nmesh: int = 200, seed: int = 5, tmin: float = 1e3, tmax: float = 5e6):
+    """Cube edge n per resident mesh: tet count T log-uniform in [tmin, tmax], n = round((T/6)^(1/3))."""
+    rng = np.random.default_rng(seed)
+    t = np.exp(rng.uniform(math.log(tmin), math.log(tmax), size=nmesh))
+    return [max(1, int(round((x / 6.0) ** (1.0 / 3.0)))) for x in t]
+
+
+def request_velocity(npoin: int, seed: int) -> np.ndarray:
+    """Per-request velocity field: U[-1,1]^3 per node from the request seed."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(npoin, 3))
