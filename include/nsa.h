@@ -1,0 +1,151 @@
+/*
+ * nsa.h -- C ABI of libnsa: P1-tetrahedron incompressible Navier-Stokes element assembly into a
+ * global block-CSR matrix plus right-hand side, on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the element loop of the paper (Brown, arXiv 2111.05651, Sec. II-A, Listing 1):
+ * for every linear tetrahedron, gather the nodal coordinates and velocities through the
+ * connectivity (Listing 2, calculate_transients), form the Cartesian shape-function derivatives,
+ * the Gauss-point values, the stabilisation parameters and the element operators, build the
+ * convective/RHS and viscous terms, and add the element contributions into the global system
+ * through the same connectivity (Listing 2, perform_assembly_in_global_system). Here the global
+ * system is a fixed-pattern block-CSR matrix with the velocity-velocity, velocity-pressure,
+ * pressure-velocity and pressure-pressure couplings (a 16x16 element matrix per tet) and a
+ * nodal RHS, rather than the paper's three nodal vectors.
+ *
+ * Conventions (all calls):
+ *   - 0-based node ids; int32 connectivity lnods[nelem][4]; FP64 coordinates coord[npoin][3] and
+ *     velocities vel[npoin][3] (dimension fastest, as coord(j, ipoin) / veloc(j, ipoin) in Listing 2).
+ *   - Degrees of freedom: 4 per node, dof = 4*node + c with c = 0,1,2 the velocity components and
+ *     c = 3 the pressure. Matrix rows are test functions, columns trial functions.
+ *   - Matrix layout: BSR with 4x4 blocks. Row i holds the blocks bptr[i] .. bptr[i+1]-1, one per node
+ *     that shares an element with node i, columns bcol[] strictly ascending; the diagonal block is
+ *     present for every node that belongs to an element (a node in no element has an empty row). values[k][c][c'] (128 bytes per block,
+ *     row-major inside the block) is the coupling of dof (row, c) with dof (bcol[k], c').
+ *     The scalar CSR view is row_ptr[4i+c] = 16*bptr[i] + 4*c*deg(i), with the 4*deg(i) entries of
+ *     that scalar row ordered by (block, c').
+ *   - rhs[npoin][4] uses the same dof order.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory of the GPU
+ *     that is current when the call is made. All device memory is owned by the caller; libnsa never
+ *     frees it. A mesh handle is owned by the caller until nsa_mesh_destroy.
+ *   - Device work is enqueued on the caller's stream (hipStream_t passed as void*; NULL = the
+ *     default stream) and is asynchronous unless stated otherwise.
+ *   - Arguments are checked on the host before anything is launched. On error nothing is launched,
+ *     outputs are left untouched, a negative nsa_status is returned and nsa_last_error() describes
+ *     the failure (thread-local).
+ */
+#ifndef NSA_H
+#define NSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nsa_status;
+#define NSA_OK 0
+#define NSA_EINVAL (-1)        /* bad argument (null pointer, negative size, bad option) */
+#define NSA_ERANGE (-2)        /* a connectivity entry outside [0, npoin) */
+#define NSA_EDEGENERATE (-3)   /* an element with det J == 0 (or not finite) */
+#define NSA_ENOMEM (-4)        /* host allocation failed, or a caller buffer is too small */
+#define NSA_EHIP (-5)          /* a HIP runtime call failed */
+#define NSA_EUNSUPPORTED (-6)  /* valid request the library cannot serve (e.g. > 128 colours) */
+#define NSA_ESTATE (-7)        /* call out of order (e.g. assemble before upload) */
+
+/* precision */
+#define NSA_FP64 0             /* everything in FP64 */
+#define NSA_MIXED 1            /* Jacobian, inverse, volume and length in FP64; element integration
+                                  in FP32; global accumulation in FP64 */
+/* scatter */
+#define NSA_ATOMIC 0           /* FP64 atomic adds into the global arrays */
+#define NSA_COLOUR 1           /* element colouring: elements of one colour share no node and add
+                                  with plain load-add-store; deterministic, bit-reproducible */
+
+typedef struct nsa_options {
+    int32_t precision;         /* NSA_FP64 or NSA_MIXED */
+    int32_t scatter;           /* NSA_ATOMIC or NSA_COLOUR */
+    int32_t accumulate;        /* 0: values/rhs are overwritten; 1: contributions are added to
+                                  what the arrays hold (the inout semantics of Listing 2) */
+    int32_t block_threads;     /* threads per workgroup, 0 = the library's choice (64..256, x64) */
+    int32_t reserved[4];       /* must be zero */
+} nsa_options;
+
+typedef struct nsa_mesh_info {
+    int64_t npoin, nelem, nnzb;
+    int32_t ncolours;
+    int32_t uploaded;          /* 1 once nsa_mesh_upload succeeded */
+    size_t ws_bytes;           /* device workspace nsa_mesh_upload needs */
+    int64_t max_row_blocks;    /* largest row degree of the block pattern */
+} nsa_mesh_info;
+
+typedef struct nsa_mesh nsa_mesh; /* opaque */
+
+/* ---- library ------------------------------------------------------------------------------- */
+
+/* Static description of a status code. Never NULL. */
+const char *nsa_status_string(nsa_status st);
+/* Detail of the last failure on this thread ("" if none). Valid until the next libnsa call on the
+ * same thread. */
+const char *nsa_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t nsa_version(void);
+
+/* ---- block pattern of the node graph (host, standalone) ------------------------------------- */
+
+/* Block-CSR pattern of a tetrahedral mesh (the fixed sparsity into which Listing 2's assembly
+ * scatters, one 4x4 block per pair of nodes that share an element).
+ *   lnods   host int32 [nelem][4], entries in [0, npoin).
+ *   bptr    host int64 [npoin+1], out: row pointers.
+ *   nnzb    out: number of blocks (= bptr[npoin]).
+ * Errors: NSA_EINVAL (null or negative sizes), NSA_ERANGE (node id out of range), NSA_ENOMEM. */
+nsa_status nsa_pattern_count(int64_t npoin, int64_t nelem, const int32_t *lnods, int64_t *bptr,
+                             int64_t *nnzb);
+/* Second phase: bcol host int32 [nnzb] (ascending per row), emap host int32 [nelem][4][4] with
+ * emap[e][a][b] = block index of (lnods[e][a], lnods[e][b]). bptr must be the output of
+ * nsa_pattern_count for the same mesh. emap may be NULL. */
+nsa_status nsa_pattern_fill(int64_t npoin, int64_t nelem, const int32_t *lnods, const int64_t *bptr,
+                            int32_t *bcol, int32_t *emap);
+
+/* ---- meshes ---------------------------------------------------------------------------------- */
+
+/* Register a mesh (host arrays are copied; the caller may free them afterwards). Validates the
+ * connectivity (NSA_ERANGE) and every element's Jacobian (NSA_EDEGENERATE, the offending element
+ * is named in nsa_last_error), builds the block pattern, the element-to-block map and a greedy
+ * element colouring (elements of one colour share no node; first-fit in element order), and the
+ * device data layout. nelem may be 0. */
+nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
+                           nsa_mesh **out);
+nsa_status nsa_mesh_destroy(nsa_mesh *m);
+nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info);
+/* Copy the block pattern out (host arrays of the sizes given by nsa_mesh_get_info: bptr
+ * [npoin+1], bcol [nnzb], emap [nelem][4][4]; any of them may be NULL). Requires the host copy
+ * (see nsa_mesh_release_host). */
+nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol, int32_t *emap);
+/* Colour classes: colour_ptr host int32 [ncolours+1], colour_elems host int32 [nelem] (element ids
+ * grouped by colour, ascending inside a colour). Either may be NULL. */
+nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems);
+/* Make the mesh device-resident: copies the connectivity, coordinates, block maps, colour lists and
+ * schedules into ws (device, at least info.ws_bytes bytes, 256-byte aligned, caller-owned and kept
+ * alive while the mesh is used). Synchronous: returns after the copies completed on the stream. */
+nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream);
+/* Drop the host copy of the pattern and element data after upload (saves host memory for large
+ * resident sets); nsa_mesh_get_pattern and nsa_mesh_get_colouring then return NSA_ESTATE. */
+nsa_status nsa_mesh_release_host(nsa_mesh *m);
+
+/* ---- assembly -------------------------------------------------------------------------------- */
+
+/* Assemble the global matrix and RHS of one uploaded mesh for the given velocity field,
+ * density rho > 0, viscosity mu >= 0 and time step dt > 0 (Listing 1's element loop with the
+ * block-CSR matrix as the target of perform_assembly_in_global_system).
+ *   vel     device FP64 [npoin][3] (the advection field and the previous-step velocity).
+ *   values  device FP64 [nnzb][4][4], rhs device FP64 [npoin][4]; 16-byte aligned; not aliased.
+ *   opt     may be NULL (FP64, atomic scatter, overwrite).
+ * Asynchronous on stream. Errors: NSA_EINVAL, NSA_ESTATE (not uploaded), NSA_EHIP (launch). */
+nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
+                        const nsa_options *opt, double *values, double *rhs, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSA_H */

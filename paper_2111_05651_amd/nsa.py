@@ -1,0 +1,204 @@
+"""Thin ctypes binding to libnsa (include/nsa.h): argument marshalling only.
+
+Every step of the assembly runs in the library's HIP kernels; PyTorch supplies device memory and
+the stream. There is no CPU fallback: if ``libnsa.so`` is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnsa.so")
+
+NSA_OK, NSA_EINVAL, NSA_ERANGE, NSA_EDEGENERATE, NSA_ENOMEM, NSA_EHIP, NSA_EUNSUPPORTED, NSA_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+FP64, MIXED = 0, 1
+ATOMIC, COLOUR = 0, 1
+
+# every symbol include/nsa.h declares
+EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
+           "nsa_mesh_create", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
+           "nsa_mesh_get_colouring", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
+
+
+class NsaError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("scatter", C.c_int32), ("accumulate", C.c_int32),
+                ("block_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("npoin", C.c_int64), ("nelem", C.c_int64), ("nnzb", C.c_int64), ("ncolours", C.c_int32),
+                ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libnsa.so from the package directory (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2111_05651_amd.build.build_library()")
+    lib = C.CDLL(path)
+    P, i32, i64, d, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    lib.nsa_status_string.argtypes = [i32]
+    lib.nsa_status_string.restype = C.c_char_p
+    lib.nsa_last_error.argtypes = []
+    lib.nsa_last_error.restype = C.c_char_p
+    lib.nsa_version.restype = i32
+    lib.nsa_pattern_count.argtypes = [i64, i64, P, P, P]
+    lib.nsa_pattern_fill.argtypes = [i64, i64, P, P, P, P]
+    lib.nsa_mesh_create.argtypes = [i64, i64, P, P, C.POINTER(P)]
+    lib.nsa_mesh_destroy.argtypes = [P]
+    lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
+    lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
+    lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
+    lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
+    lib.nsa_mesh_release_host.argtypes = [P]
+    lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
+    for name in EXPORTS:
+        if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str):
+    if st != NSA_OK:
+        lib = load()
+        raise NsaError(st, where, lib.nsa_last_error().decode() or lib.nsa_status_string(st).decode())
+
+
+def _ptr(a) -> int:
+    """Address of a NumPy array or a torch tensor (CPU or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def pattern(npoin: int, lnods: np.ndarray):
+    """Block-CSR pattern (bptr int64, bcol int32, emap int32 [nelem][4][4]) via the library."""
+    lib = load()
+    ln = np.ascontiguousarray(lnods, dtype=np.int32)
+    nelem = ln.shape[0]
+    bptr = np.zeros(npoin + 1, dtype=np.int64)
+    nnzb = np.zeros(1, dtype=np.int64)
+    _check(lib.nsa_pattern_count(npoin, nelem, _ptr(ln), _ptr(bptr), _ptr(nnzb)), "nsa_pattern_count")
+    bcol = np.zeros(int(nnzb[0]), dtype=np.int32)
+    emap = np.zeros((nelem, 4, 4), dtype=np.int32)
+    _check(lib.nsa_pattern_fill(npoin, nelem, _ptr(ln), _ptr(bptr), _ptr(bcol), _ptr(emap)), "nsa_pattern_fill")
+    return bptr, bcol, emap
+
+
+class Mesh:
+    """A registered mesh (host handle) and, after upload(), its device workspace (a torch tensor)."""
+
+    def __init__(self, lnods: np.ndarray, coord: np.ndarray):
+        lib = load()
+        ln = np.ascontiguousarray(lnods, dtype=np.int32)
+        co = np.ascontiguousarray(coord, dtype=np.float64)
+        if ln.ndim != 2 or ln.shape[1] != 4 or co.ndim != 2 or co.shape[1] != 3:
+            raise ValueError("lnods must be [nelem][4] and coord [npoin][3]")
+        h = C.c_void_p()
+        _check(lib.nsa_mesh_create(co.shape[0], ln.shape[0], _ptr(ln), _ptr(co), C.byref(h)), "nsa_mesh_create")
+        self._h = h
+        self.ws = None
+        self.info = self._info()
+
+    @classmethod
+    def from_inputs(cls, m) -> "Mesh":
+        return cls(m.lnods, m.coord)
+
+    def _info(self) -> MeshInfo:
+        info = MeshInfo()
+        _check(load().nsa_mesh_get_info(self._h, C.byref(info)), "nsa_mesh_get_info")
+        return info
+
+    @property
+    def npoin(self):
+        return self.info.npoin
+
+    @property
+    def nelem(self):
+        return self.info.nelem
+
+    @property
+    def nnzb(self):
+        return self.info.nnzb
+
+    def pattern(self):
+        i = self.info
+        bptr = np.zeros(i.npoin + 1, dtype=np.int64)
+        bcol = np.zeros(i.nnzb, dtype=np.int32)
+        emap = np.zeros((i.nelem, 4, 4), dtype=np.int32)
+        _check(load().nsa_mesh_get_pattern(self._h, _ptr(bptr), _ptr(bcol), _ptr(emap)), "nsa_mesh_get_pattern")
+        return bptr, bcol, emap
+
+    def colouring(self):
+        i = self.info
+        cptr = np.zeros(i.ncolours + 1, dtype=np.int32)
+        celems = np.zeros(i.nelem, dtype=np.int32)
+        _check(load().nsa_mesh_get_colouring(self._h, _ptr(cptr), _ptr(celems)), "nsa_mesh_get_colouring")
+        return cptr, celems
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        nbytes = int(self.info.ws_bytes)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _check(load().nsa_mesh_upload(self._h, self.ws.data_ptr(), nbytes, _stream_handle(stream)),
+               "nsa_mesh_upload")
+        self.info = self._info()
+        return self
+
+    def release_host(self):
+        _check(load().nsa_mesh_release_host(self._h), "nsa_mesh_release_host")
+
+    def alloc_outputs(self, device="cuda"):
+        import torch
+        values = torch.empty((self.nnzb, 4, 4), dtype=torch.float64, device=device)
+        rhs = torch.empty((self.npoin, 4), dtype=torch.float64, device=device)
+        return values, rhs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.nsa_mesh_destroy(h)
+            self._h = None
+
+
+def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads=0) -> Options:
+    o = Options()
+    o.precision, o.scatter, o.accumulate, o.block_threads = int(precision), int(scatter), int(accumulate), int(block_threads)
+    return o
+
+
+def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP64, scatter=ATOMIC,
+             accumulate=False, block_threads=0, values=None, rhs=None, stream=None):
+    """Launch nsa_assemble on the stream (default: torch's current stream); returns (values, rhs)
+    as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given)."""
+    if values is None or rhs is None:
+        values, rhs = mesh.alloc_outputs(vel.device)
+    o = make_options(precision, scatter, accumulate, block_threads)
+    _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
+                               _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
+    return values, rhs

@@ -1,0 +1,130 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle on the same seeded inputs.
+
+Bar (block-class metric of parity.py): 1e-12 for FP64, 1e-5 for the mixed form; the pattern and
+element-to-block map bit-exact; the colouring path bit-identical run to run."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_05651_amd import inputs, nsa
+from tests.parity import TOL_FP64, TOL_MIXED, assert_parity, class_errors
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MODES = [(nsa.FP64, nsa.ATOMIC), (nsa.FP64, nsa.COLOUR), (nsa.MIXED, nsa.ATOMIC), (nsa.MIXED, nsa.COLOUR)]
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_assemble(mesh, m, precision, scatter, vel=None, **kw):
+    v = torch.from_numpy(m.velocity if vel is None else vel).cuda()
+    values, rhs = nsa.assemble(mesh, v, kw.pop("rho", m.rho), kw.pop("mu", m.mu), kw.pop("dt", m.dt),
+                               precision=precision, scatter=scatter, **kw)
+    torch.cuda.synchronize()
+    return values.cpu().numpy(), rhs.cpu().numpy()
+
+
+def tol_of(precision):
+    return TOL_FP64 if precision == nsa.FP64 else TOL_MIXED
+
+
+@pytest.mark.parametrize("cfg", ["cube8", "cube7_perm", "cube5_rcm", "cube3"])
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"{'fp64' if m[0] == 0 else 'mixed'}-{'atomic' if m[1] == 0 else 'colour'}")
+def test_small_meshes(cfg, mode):
+    m = {"cube8": inputs.config_small,
+         "cube7_perm": lambda: inputs.make_mesh(7, jitter=True, permute=True, velocity="vortex", seed=17),
+         "cube5_rcm": lambda: inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=18),
+         "cube3": lambda: inputs.make_mesh(3, jitter=True, velocity="uniform", seed=19, rho=1.7, mu=3e-2, dt=2e-3)}[cfg]()
+    say(f"[parity] {cfg} nelem={m.nelem} mode={mode}")
+    ref_v, ref_r = oracle.assemble(m)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    v, r = gpu_assemble(mesh, m, *mode)
+    assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"{cfg} {mode}")
+
+
+def test_degenerate_parameters():
+    """mu = 0 with zero velocity (pure mass/Laplacian), huge and tiny dt, zero velocity RHS."""
+    m = inputs.make_mesh(4, jitter=True, permute=True, seed=23)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    for rho, mu, dt, vel in ((1.0, 0.0, 1e-2, np.zeros_like(m.velocity)), (2.0, 1e-3, 1e6, m.velocity),
+                             (0.5, 1e-1, 1e-9, m.velocity), (1.0, 1e-3, 1e-2, np.zeros_like(m.velocity))):
+        ref_v, ref_r = oracle.assemble(m, rho=rho, mu=mu, dt=dt, velocity=vel)
+        for mode in MODES:
+            v, r = gpu_assemble(mesh, m, *mode, vel=vel, rho=rho, mu=mu, dt=dt)
+            err = class_errors(v, ref_v, r, ref_r)
+            for k, e in err.items():
+                if k.startswith("rhs") and np.abs(ref_r).max() == 0:
+                    assert np.abs(r).max() == 0
+                    continue
+                assert e <= tol_of(mode[0]), (rho, mu, dt, mode, err)
+
+
+def test_accumulate():
+    m = inputs.make_mesh(4, jitter=True, permute=True, seed=24)
+    ref_v, ref_r = oracle.assemble(m)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    vel = torch.from_numpy(m.velocity).cuda()
+    values, rhs = mesh.alloc_outputs()
+    values.fill_(1.0)
+    rhs.fill_(-2.0)
+    for scatter in (nsa.ATOMIC, nsa.COLOUR):
+        values.fill_(1.0)
+        rhs.fill_(-2.0)
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=scatter, accumulate=True, values=values, rhs=rhs)
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=scatter, accumulate=True, values=values, rhs=rhs)
+        torch.cuda.synchronize()
+        assert_parity(values.cpu().numpy() - 1.0, 2 * ref_v, rhs.cpu().numpy() + 2.0, 2 * ref_r, 1e-12)
+
+
+def test_colour_path_bit_reproducible():
+    m = inputs.make_mesh(12, jitter=True, permute=True, velocity="vortex", seed=25)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    for prec in (nsa.FP64, nsa.MIXED):
+        v0, r0 = gpu_assemble(mesh, m, prec, nsa.COLOUR)
+        for _ in range(9):
+            v, r = gpu_assemble(mesh, m, prec, nsa.COLOUR)
+            assert np.array_equal(v, v0) and np.array_equal(r, r0)
+
+
+def test_empty_and_tiny():
+    mesh = nsa.Mesh(np.zeros((0, 4), np.int32), np.zeros((3, 3))).upload()
+    vel = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    values, rhs = mesh.alloc_outputs()
+    rhs.fill_(7.0)
+    nsa.assemble(mesh, vel, 1.0, 1e-3, 1e-2, values=values, rhs=rhs)
+    torch.cuda.synchronize()
+    assert values.numel() == 0 and torch.all(rhs == 0)
+    m = inputs.make_mesh(1, jitter=True, seed=26)           # 6 tets
+    ref_v, ref_r = oracle.assemble(m)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    for mode in MODES:
+        v, r = gpu_assemble(mesh, m, *mode)
+        assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"one hex {mode}")
+
+
+@pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
+def test_cube64_full(scatter):
+    """The 64^3 workload (1,572,864 tets, nodes randomly permuted), every entry against the oracle."""
+    m = inputs.config_64()
+    say(f"[parity] cube64 nelem={m.nelem} scatter={scatter}: oracle ...")
+    pat = oracle.pattern(m.npoin, m.lnods)
+    ref_v, ref_r = oracle.assemble(m, pat)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    bptr, bcol, emap = mesh.pattern()
+    assert np.array_equal(bptr, pat[0]) and np.array_equal(bcol, pat[1]) and np.array_equal(emap, pat[2])
+    for prec in (nsa.FP64, nsa.MIXED):
+        say(f"[parity] cube64 precision={prec} scatter={scatter}")
+        v, r = gpu_assemble(mesh, m, prec, scatter)
+        err = assert_parity(v, ref_v, r, ref_r, tol_of(prec), f"cube64 {prec} {scatter}")
+        say(f"[parity] cube64 errors {err}")
