@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of P1-tet incompressible Navier-Stokes assembly on one MI355X.
+
+One step = one nsa_assemble call: every element of the mesh gathered, integrated and added into
+the block-CSR matrix and RHS (values and RHS overwritten), inputs already resident in HBM.
+Default workload: the 128^3 Kuhn cube (12,582,912 tets, 2,146,689 nodes, 31,802,497 4x4 blocks),
+jittered, randomly permuted then RCM-renumbered, elements sorted by smallest node, Taylor-Green
+velocity plus 1% noise, rho=1, mu=1e-3, dt=5e-3. The headline precision is the mixed form (FP64
+geometry and accumulation, FP32 element integration); the plain FP64 kernel is timed beside it on
+the same GPU. Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2111_05651_amd", "csrc", "nsa_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nelem, npoin, nnzb):
+    """Bytes the method must move once: connectivity (16/elem), coordinates + velocity (48/node),
+    every block written once (128/block), RHS (32/node)."""
+    return 16 * nelem + 48 * npoin + 128 * nnzb + 32 * npoin
+
+
+def source_digest():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def make_workload(name):
+    from paper_2111_05651_amd import inputs
+    return {"cube128": inputs.config_128, "cube64": inputs.config_64, "cube8": inputs.config_small}[name]()
+
+
+def time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s, e in evs:
+        s.record(stream)
+        fn()
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [s.elapsed_time(e) for s, e in evs]
+    total = evs[0][0].elapsed_time(evs[-1][1])
+    return total / steps, per, wall
+
+
+def class_diff(a_values, a_rhs, b_values, b_rhs):
+    """Per block class {uu, up, pu, pp} and RHS class {u, p}: max|a - b| / max|b|."""
+    out = {}
+    sl = {"uu": (slice(0, 3), slice(0, 3)), "up": (slice(0, 3), slice(3, 4)), "pu": (slice(3, 4), slice(0, 3)),
+          "pp": (slice(3, 4), slice(3, 4))}
+    for k, (i, j) in sl.items():
+        ref = b_values[:, i, j]
+        out[k] = float((a_values[:, i, j] - ref).abs().max() / ref.abs().max())
+    for k, c in (("rhs_u", slice(0, 3)), ("rhs_p", slice(3, 4))):
+        ref = b_rhs[:, c]
+        den = ref.abs().max()
+        out[k] = float((a_rhs[:, c] - ref).abs().max() / den) if den > 0 else float((a_rhs[:, c] - ref).abs().max())
+    return out
+
+
+def cpu_baseline(m, nelem_sample):
+    """The oracle (serial C, FP64) on the first nelem_sample elements of the same mesh."""
+    import oracle
+    from paper_2111_05651_amd import inputs
+    sub = inputs.Mesh(n=m.n, lnods=m.lnods[:nelem_sample].copy(), coord=m.coord, velocity=m.velocity,
+                      rho=m.rho, mu=m.mu, dt=m.dt)
+    pat = oracle.pattern(sub.npoin, sub.lnods)
+    t0 = time.perf_counter()
+    oracle.assemble(sub, pat)
+    dt = time.perf_counter() - t0
+    return {"value": nelem_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nelem_sample} elements of the same mesh, serial FP64 C oracle "
+                      f"(pattern build untimed), {dt:.1f} s"}
+
+
+def traffic_for(kernel_key, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on this
+    exact kernel source and configuration; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    rec = t.get(kernel_key)
+    if not rec or rec.get("source_sha256") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
+    ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto"])
+    ap.add_argument("--tile-blocks", type=int, default=512)
+    ap.add_argument("--no-baseline-fp64", action="store_true", help="skip timing the FP64 kernel beside")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="instead: time a plain device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2111_05651_amd import nsa
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    nsa.load()
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        ms, per, _ = time_steps(lambda: dst.copy_(src), args.steps, args.warmup, torch.cuda.current_stream())
+        print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n, "ms": ms,
+                          "GBs_read_plus_write": 16 * n / (ms / 1e3) / 1e9}), flush=True)
+        return
+    prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
+    scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
+    kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO}[args.kernel]
+
+    t0 = time.perf_counter()
+    m = make_workload(args.workload)
+    log(f"workload {args.workload}: {m.nelem} tets, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=args.tile_blocks)
+    mesh.upload("cuda:0")
+    info = mesh.info
+    log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles} tile_elems/nelem="
+        f"{info.tile_elems / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes}")
+    vel = torch.from_numpy(m.velocity).to("cuda:0")
+    values, rhs = mesh.alloc_outputs("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step(p=prec):
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=p, scatter=scat, kernel=kern, values=values,
+                     rhs=rhs, stream=stream)
+
+    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
+    fp64 = None
+    if prec == nsa.MIXED and not args.no_baseline_fp64:
+        mixed_v, mixed_r = values.clone(), rhs.clone()
+        ms64, per64, _ = time_steps(lambda: step(nsa.FP64), args.steps, args.warmup, stream)
+        diff = class_diff(mixed_v, mixed_r, values, rhs)
+        del mixed_v, mixed_r
+        fp64 = {"value": m.nelem / (ms64 / 1e3), "ms_per_step": ms64, "unit": "elements/s",
+                "dtype": "f64", "same_gpu": True, "mixed_vs_fp64_class_error": diff}
+        log(f"FP64 kernel beside it: {ms64:.4f} ms/step; mixed vs FP64 class errors {diff}")
+
+    nbytes = algorithmic_bytes(m.nelem, m.npoin, info.nnzb)
+    launch_ms = statistics.fmean(per)
+    achieved = nbytes / (launch_ms / 1e3) / 1e9
+    kname = f"k_tiled<{'float' if prec == nsa.MIXED else 'double'},{'colour' if scat == nsa.COLOUR else 'atomic'}>"
+    key = f"{kname}@{args.workload}/tile{args.tile_blocks}"
+    traffic = traffic_for(key, nbytes) if kern == nsa.KERNEL_TILED else None
+    line = {
+        "metric": "elements assembled/s",
+        "value": m.nelem / (ms / 1e3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == nsa.MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {m.name}", "nelem": m.nelem, "npoin": m.npoin,
+                   "nnzb": info.nnzb, "precision": args.precision, "scatter": args.scatter,
+                   "kernel": args.kernel, "tile_blocks": args.tile_blocks, "rho": m.rho, "mu": m.mu, "dt": m.dt},
+        "hbm_GBs": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
+                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": launch_ms},
+        "fp64_baseline": fp64,
+    }
+    if not args.no_cpu_baseline:
+        ns = min(args.cpu_sample, m.nelem)
+        log(f"cpu baseline: oracle on {ns} elements ...")
+        line["cpu_baseline"] = cpu_baseline(m, ns)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

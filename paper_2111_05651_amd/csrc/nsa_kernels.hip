@@ -246,4 +246,336 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
     return hipGetLastError();
 }
 
+// ================================================================================================
+// Row-tiled assembly (the default path).
+//
+// One workgroup owns a tile of contiguous block rows and the contiguous range of blocks they hold.
+// It keeps an FP64 image of those blocks (and of the tile's RHS rows) in LDS, runs every element
+// that touches one of its rows, adds the contributions of the owned rows into the LDS image, and
+// finally writes the image to HBM once, coalesced. No global atomics, no zero-fill pass, and every
+// value line is written exactly once. Elements on a tile boundary are evaluated by each tile they
+// touch; only their owned rows are integrated there.
+//
+// Duplicate targets inside a tile are reduced in LDS, either with FP64 LDS atomics (ds_add_f64) in
+// the atomic mode, or in the colour mode by processing the tile's elements colour by colour
+// (elements of one tile colour share no owned node), so every LDS block is updated with a plain
+// read-add-write in a fixed order and the result is bit-reproducible.
+//
+// Inside an element the local nodes are reordered so that the owned ones come first; the plan sorts
+// each tile's elements (inside a colour) by how many rows they own, so the lanes of a wavefront run
+// the same number of row iterations.
+// ================================================================================================
+namespace {
+
+// Reciprocal: hardware estimate refined by two Newton steps (full FP64 accuracy for normal x).
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// x^(-1/3) for x > 0: FP32 estimate (2^(-log2(x)/3)) refined by Newton steps r += r (1 - x r^3) / 3.
+__device__ __forceinline__ double rcbrt(double x) {
+    if (!(x > 1e-30 && x < 1e30)) return 1.0 / cbrt(x);  // outside the FP32 estimate's range
+    float xf = (float)x;
+    double r = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * (1.0f / 3.0f));
+#pragma unroll
+    for (int it = 0; it < 3; it++) r = fma(r * (1.0 / 3.0), fma(-x * r, r * r, 1.0), r);
+    return r;
+}
+
+// Geometry in FP64: grad N_a, V, h = (6V)^(1/3) = |det|^(1/3) and 1/h.
+struct Geo2 {
+    double G[4][3];
+    double V, h, rh;
+};
+
+__device__ __forceinline__ void geometry2(const double X[4][3], Geo2 &g) {
+    double J[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) J[r][s] = X[s + 1][r] - X[0][r];
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double inv = fast_rcp(det);
+    g.G[1][0] = c00 * inv; g.G[1][1] = c10 * inv; g.G[1][2] = c20 * inv;
+    g.G[2][0] = c01 * inv; g.G[2][1] = c11 * inv; g.G[2][2] = c21 * inv;
+    g.G[3][0] = c02 * inv; g.G[3][1] = c12 * inv; g.G[3][2] = c22 * inv;
+#pragma unroll
+    for (int d = 0; d < 3; d++) g.G[0][d] = -(g.G[1][d] + g.G[2][d] + g.G[3][d]);
+    const double adet = fabs(det);
+    g.V = adet * (1.0 / 6.0);
+    g.rh = rcbrt(adet);
+    g.h = adet * g.rh * g.rh;
+}
+
+// Element state in the integration precision R, for the closed-form integrals of the header.
+template <typename R>
+struct ElemT {
+    R G[4][3];
+    R d[4][4];   // d[k][b] = U_k . grad N_b
+    R s[4];      // s_b = sum_k d[k][b]
+    R U[4][3];
+    R su[3];     // sum_k U_k
+    R rdt, rho, v4, v20, muV, t2V, t1V, t1, t1rho;
+    R Mo, Md;    // mass coefficients (rho/dt) V/20 for a != b and a == b
+    R c1, c2, c3;  // rho V/20, tau1 rho^2 V/20, tau1 rho (rho/dt) V/20
+};
+
+template <typename R>
+__device__ __forceinline__ void setup_t(const Geo2 &g, const double Ud[4][3], double rho_d, double mu_d, double dt_d,
+                                        ElemT<R> &E) {
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            E.U[a][c] = (R)Ud[a][c];
+            E.G[a][c] = (R)g.G[a][c];
+        }
+    const R V = (R)g.V, h = (R)g.h, rh = (R)g.rh, rho = (R)rho_d, mu = (R)mu_d;
+    const R rdt = (R)(rho_d / dt_d);
+#pragma unroll
+    for (int c = 0; c < 3; c++) E.su[c] = E.U[0][c] + E.U[1][c] + E.U[2][c] + E.U[3][c];
+    const R an = (R)0.25 * sqrt(E.su[0] * E.su[0] + E.su[1] * E.su[1] + E.su[2] * E.su[2]);
+    const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
+    const R t2 = mu + (R)0.5 * rho * an * h;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) E.d[k][b] = E.U[k][0] * E.G[b][0] + E.U[k][1] * E.G[b][1] + E.U[k][2] * E.G[b][2];
+#pragma unroll
+    for (int b = 0; b < 4; b++) E.s[b] = E.d[0][b] + E.d[1][b] + E.d[2][b] + E.d[3][b];
+    E.rdt = rdt;
+    E.rho = rho;
+    E.v4 = V * (R)0.25;
+    E.v20 = V * (R)0.05;
+    E.muV = mu * V;
+    E.t2V = t2 * V;
+    E.t1V = t1 * V;
+    E.t1 = t1;
+    E.t1rho = t1 * rho;
+    E.Mo = rdt * E.v20;
+    E.Md = E.Mo + E.Mo;
+    E.c1 = rho * E.v20;
+    E.c2 = E.t1rho * rho * E.v20;
+    E.c3 = E.t1rho * rdt * E.v20;
+}
+
+// Row a of the element: RHS (4 values) and the four 4x4 blocks (a, b), each handed to put(b, blk).
+template <typename R, typename Put>
+__device__ __forceinline__ void element_row(const ElemT<R> &E, int a, R rb[4], Put put) {
+    const R ga0 = E.G[a][0], ga1 = E.G[a][1], ga2 = E.G[a][2], sa = E.s[a];
+    // RHS: (rho/dt) int u_c N_a + tau1 rho (rho/dt) int (a.grad N_a) u_c ; PSPG tau1 (rho/dt) V/4 s_a
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const R un = E.v20 * (E.su[c] + E.U[a][c]);
+        const R au = E.v20 * (sa * E.su[c] + E.d[0][a] * E.U[0][c] + E.d[1][a] * E.U[1][c] +
+                              E.d[2][a] * E.U[2][c] + E.d[3][a] * E.U[3][c]);
+        rb[c] = E.rdt * (un + E.t1rho * au);
+    }
+    rb[3] = E.t1 * E.rdt * E.v4 * sa;
+    const R gm[3] = {E.muV * ga0, E.muV * ga1, E.muV * ga2};
+    const R gt[3] = {E.t2V * ga0, E.t2V * ga1, E.t2V * ga2};
+    const R pa[3] = {-E.v4 * ga0, -E.v4 * ga1, -E.v4 * ga2};
+    const R tg[3] = {E.t1 * ga0, E.t1 * ga1, E.t1 * ga2};
+    const R qa = E.t1rho * E.v4 * sa;
+    const R c2sa = E.c2 * sa;
+    const R c3sa = E.c3 * sa;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        const R gb0 = E.G[b][0], gb1 = E.G[b][1], gb2 = E.G[b][2], sb = E.s[b];
+        const R K = ga0 * gb0 + ga1 * gb1 + ga2 * gb2;
+        const R gram = E.d[0][a] * E.d[0][b] + E.d[1][a] * E.d[1][b] + E.d[2][a] * E.d[2][b] + E.d[3][a] * E.d[3][b];
+        const R T = (a == b ? E.Md : E.Mo) + E.c1 * (sb + E.d[a][b]) + E.muV * K + c2sa * sb + E.c2 * gram +
+                    c3sa + E.c3 * E.d[b][a];
+        const R gbv[3] = {gb0, gb1, gb2};
+        R blk[16];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int cp = 0; cp < 3; cp++) {
+                const R v = gm[cp] * gbv[c] + gt[c] * gbv[cp];
+                blk[4 * c + cp] = (c == cp) ? v + T : v;
+            }
+        const R rbb = E.rho * E.v4 * sb + E.rdt * E.v4;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            blk[4 * c + 3] = pa[c] + qa * gbv[c];
+            blk[12 + c] = E.v4 * gbv[c] + tg[c] * rbb;
+        }
+        blk[15] = E.t1V * K;
+        put(b, blk);
+    }
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v, bool colour) {
+    if (colour)
+        *p += v;
+    else
+        __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One element of the tile from its record: node data from the LDS node table, owned rows first.
+template <typename R, bool COLOUR>
+__device__ __forceinline__ void tile_element(const TileArgs &A, int64_t p, int nrows, double *acc, double *racc,
+                                             const double *nodes, const int *rowoff) {
+    const uint2 w0 = A.rec[3 * p], w1 = A.rec[3 * p + 1], w2 = A.rec[3 * p + 2];
+    const int loc[4] = {(int)(w0.x & 0xffffu), (int)(w0.x >> 16), (int)(w0.y & 0xffffu), (int)(w0.y >> 16)};
+    const uint32_t rw[4] = {w1.x, w1.y, w2.x, w2.y};
+    int nown = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) nown += loc[a] < nrows;
+    double X[4][3], U[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const double2 *nd = reinterpret_cast<const double2 *>(nodes + 6 * loc[a]);
+        const double2 q0 = nd[0], q1 = nd[1], q2 = nd[2];
+        X[a][0] = q0.x;
+        X[a][1] = q0.y;
+        X[a][2] = q1.x;
+        U[a][0] = q1.y;
+        U[a][1] = q2.x;
+        U[a][2] = q2.y;
+    }
+    Geo2 g;
+    geometry2(X, g);
+    ElemT<R> E;
+    setup_t<R>(g, U, A.rho, A.mu, A.dt, E);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        if (a >= nown) break;
+        const int lr = loc[a];
+        const int base = rowoff[lr];
+        int slot[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) slot[b] = base + (int)((rw[a] >> (8 * b)) & 0xffu);
+        R rb[4];
+        element_row<R>(E, a, rb, [&](int b, const R *blk) {
+            double *q = acc + kBlkStride * slot[b];
+#pragma unroll
+            for (int i = 0; i < 16; i++) lds_add(q + i, (double)blk[i], COLOUR);
+        });
+        double *q = racc + kRhsStride * lr;
+#pragma unroll
+        for (int c = 0; c < 4; c++) lds_add(q + c, (double)rb[c], COLOUR);
+    }
+}
+
+template <typename R, bool COLOUR, int NT>
+__global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
+    extern __shared__ double smem[];
+    // XCD-aware order: workgroup w runs on XCD w % 8, so give each XCD a contiguous run of tiles
+    // (neighbouring tiles share nodal data in that XCD's L2).
+    const int64_t per = (A.ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= A.ntiles) return;
+    const int tid = threadIdx.x;
+    const int r0 = A.tile_row[tile], r1 = A.tile_row[tile + 1], nrows = r1 - r0;
+    const int64_t b0 = A.bptr[r0];
+    const int nblk = (int)(A.bptr[r1] - b0);
+    const int64_t n0 = A.tile_nptr[tile];
+    const int nnod = (int)(A.tile_nptr[tile + 1] - n0);
+    // block image at a padded stride (a block's 16 values sit at immediate offsets from one base and
+    // neighbouring slots start on different banks), RHS rows, node table, row offsets
+    double *acc = smem;
+    double *racc = smem + lds_racc_off(nblk);
+    double *nodes = smem + lds_nodes_off(nblk, nrows);
+    int *rowoff = reinterpret_cast<int *>(smem + lds_rowoff_off(nblk, nrows, nnod));
+    for (int i = tid; i < nrows; i += NT) rowoff[i] = (int)(A.bptr[r0 + i] - b0);
+    for (int i = tid; i < nnod; i += NT) {
+        const int64_t gnode = A.tile_nodes[n0 + i];
+        const double4 c = A.coord[gnode];
+        const double *v = A.vel + 3 * gnode;
+        double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
+        nd[0] = make_double2(c.x, c.y);
+        nd[1] = make_double2(c.z, v[0]);
+        nd[2] = make_double2(v[1], v[2]);
+    }
+    for (int i = tid; i < kBlkStride * nblk; i += NT) acc[i] = 0.0;
+    for (int i = tid; i < kRhsStride * nrows; i += NT) racc[i] = 0.0;
+    __syncthreads();
+    const int64_t p0 = A.tile_eptr[tile];
+    if (!COLOUR) {
+        const int64_t p1 = A.tile_eptr[tile + 1];
+        for (int64_t p = p0 + tid; p < p1; p += NT) tile_element<R, false>(A, p, nrows, acc, racc, nodes, rowoff);
+    } else {
+        const int32_t *cc = A.ccnt + A.tile_cptr[tile];
+        const int ncol = A.tile_cptr[tile + 1] - A.tile_cptr[tile] - 1;
+        for (int c = 0; c < ncol; c++) {
+            for (int64_t p = p0 + cc[c] + tid; p < p0 + cc[c + 1]; p += NT)
+                tile_element<R, true>(A, p, nrows, acc, racc, nodes, rowoff);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // write the image out: block k, value pair j -> values[(b0 + k) * 16 + 2j]
+    double2 *out = reinterpret_cast<double2 *>(A.values + 16 * b0);
+    for (int i = tid; i < 8 * nblk; i += NT) {
+        const int k = i >> 3, j = i & 7;
+        const double *src = acc + kBlkStride * k + 2 * j;
+        double2 v = make_double2(src[0], src[1]);
+        if (A.accumulate) {
+            const double2 o = out[i];
+            v.x += o.x;
+            v.y += o.y;
+        }
+        out[i] = v;
+    }
+    double *rout = A.rhs + 4 * (int64_t)r0;
+    for (int i = tid; i < 4 * nrows; i += NT) {
+        const int r = i >> 2, c = i & 3;
+        double v = racc[kRhsStride * r + c];
+        if (A.accumulate) v += rout[i];
+        rout[i] = v;
+    }
+}
+
+}  // namespace
+
+size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
+    return (size_t)lds_rowoff_off(cap_blocks, cap_rows, cap_nodes) * 8 + (size_t)cap_rows * 4;
+}
+
+hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)a.lds_bytes;
+    const int64_t per = (a.ntiles + 7) / 8;
+    const int nt = a.threads == 128 ? 128 : 256;
+    const dim3 grid((unsigned)(8 * per)), block(nt);
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+        return hipGetLastError();
+    };
+    if (nt == 128) {
+        switch (k) {
+            case TileKern::AtomicF64: return go(k_tiled<double, false, 128>);
+            case TileKern::AtomicMixed: return go(k_tiled<float, false, 128>);
+            case TileKern::ColourF64: return go(k_tiled<double, true, 128>);
+            case TileKern::ColourMixed: return go(k_tiled<float, true, 128>);
+        }
+    } else {
+        switch (k) {
+            case TileKern::AtomicF64: return go(k_tiled<double, false, 256>);
+            case TileKern::AtomicMixed: return go(k_tiled<float, false, 256>);
+            case TileKern::ColourF64: return go(k_tiled<double, true, 256>);
+            case TileKern::ColourMixed: return go(k_tiled<float, true, 256>);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace nsa

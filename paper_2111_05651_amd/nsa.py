@@ -17,11 +17,12 @@ NSA_OK, NSA_EINVAL, NSA_ERANGE, NSA_EDEGENERATE, NSA_ENOMEM, NSA_EHIP, NSA_EUNSU
     0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 ATOMIC, COLOUR = 0, 1
+KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT = 0, 1, 2
 
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
-           "nsa_mesh_create", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
-           "nsa_mesh_get_colouring", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
+           "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
+           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_tile_records", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
 
 
 class NsaError(RuntimeError):
@@ -32,12 +33,14 @@ class NsaError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("scatter", C.c_int32), ("accumulate", C.c_int32),
-                ("block_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("block_threads", C.c_int32), ("kernel", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class MeshInfo(C.Structure):
     _fields_ = [("npoin", C.c_int64), ("nelem", C.c_int64), ("nnzb", C.c_int64), ("ncolours", C.c_int32),
-                ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64)]
+                ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64),
+                ("ntiles", C.c_int64), ("tile_elems", C.c_int64), ("tile_blocks", C.c_int32),
+                ("tile_max_colours", C.c_int32), ("tile_lds_bytes", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -60,10 +63,13 @@ def load(path: str = LIB_PATH):
     lib.nsa_pattern_count.argtypes = [i64, i64, P, P, P]
     lib.nsa_pattern_fill.argtypes = [i64, i64, P, P, P, P]
     lib.nsa_mesh_create.argtypes = [i64, i64, P, P, C.POINTER(P)]
+    lib.nsa_mesh_set_tiling.argtypes = [P, i32]
     lib.nsa_mesh_destroy.argtypes = [P]
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
     lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
+    lib.nsa_mesh_get_tiles.argtypes = [P, P, P, P, P, P, P]
+    lib.nsa_mesh_get_tile_records.argtypes = [P, P, P, P, P]
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
     lib.nsa_mesh_release_host.argtypes = [P]
     lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
@@ -113,7 +119,7 @@ def pattern(npoin: int, lnods: np.ndarray):
 class Mesh:
     """A registered mesh (host handle) and, after upload(), its device workspace (a torch tensor)."""
 
-    def __init__(self, lnods: np.ndarray, coord: np.ndarray):
+    def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -123,11 +129,17 @@ class Mesh:
         _check(lib.nsa_mesh_create(co.shape[0], ln.shape[0], _ptr(ln), _ptr(co), C.byref(h)), "nsa_mesh_create")
         self._h = h
         self.ws = None
+        if tile_blocks is not None:
+            _check(lib.nsa_mesh_set_tiling(h, int(tile_blocks)), "nsa_mesh_set_tiling")
         self.info = self._info()
 
     @classmethod
-    def from_inputs(cls, m) -> "Mesh":
-        return cls(m.lnods, m.coord)
+    def from_inputs(cls, m, tile_blocks: int | None = None) -> "Mesh":
+        return cls(m.lnods, m.coord, tile_blocks)
+
+    def set_tiling(self, tile_blocks: int):
+        _check(load().nsa_mesh_set_tiling(self._h, int(tile_blocks)), "nsa_mesh_set_tiling")
+        self.info = self._info()
 
     def _info(self) -> MeshInfo:
         info = MeshInfo()
@@ -161,6 +173,28 @@ class Mesh:
         _check(load().nsa_mesh_get_colouring(self._h, _ptr(cptr), _ptr(celems)), "nsa_mesh_get_colouring")
         return cptr, celems
 
+    def tiles(self):
+        """Row-tile plan: dict of tile_row, tile_eptr, elems_atomic, elems_colour, tile_cptr, ccnt."""
+        i = self.info
+        out = dict(tile_row=np.zeros(i.ntiles + 1, np.int32), tile_eptr=np.zeros(i.ntiles + 1, np.int64),
+                   elems_atomic=np.zeros(i.tile_elems, np.int32), elems_colour=np.zeros(i.tile_elems, np.int32),
+                   tile_cptr=np.zeros(i.ntiles + 1, np.int32))
+        _check(load().nsa_mesh_get_tiles(self._h, _ptr(out["tile_row"]), _ptr(out["tile_eptr"]), None, None,
+                                          _ptr(out["tile_cptr"]), None), "nsa_mesh_get_tiles")
+        out["ccnt"] = np.zeros(int(out["tile_cptr"][-1]), np.int32)
+        _check(load().nsa_mesh_get_tiles(self._h, None, None, _ptr(out["elems_atomic"]), _ptr(out["elems_colour"]),
+                                          None, _ptr(out["ccnt"])), "nsa_mesh_get_tiles")
+        nptr = np.zeros(i.ntiles + 1, np.int64)
+        _check(load().nsa_mesh_get_tile_records(self._h, _ptr(nptr), None, None, None), "nsa_mesh_get_tile_records")
+        rec_dt = np.dtype([("loc", np.uint16, (4,)), ("rank", np.uint8, (4, 4))])
+        out["tile_nptr"] = nptr
+        out["tile_nodes"] = np.zeros(int(nptr[-1]), np.int32)
+        out["rec_atomic"] = np.zeros(i.tile_elems, rec_dt)
+        out["rec_colour"] = np.zeros(i.tile_elems, rec_dt)
+        _check(load().nsa_mesh_get_tile_records(self._h, None, _ptr(out["tile_nodes"]), _ptr(out["rec_atomic"]),
+                                                _ptr(out["rec_colour"])), "nsa_mesh_get_tile_records")
+        return out
+
     def upload(self, device="cuda", stream=None):
         import torch
         nbytes = int(self.info.ws_bytes)
@@ -186,19 +220,20 @@ class Mesh:
             self._h = None
 
 
-def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads=0) -> Options:
+def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads=0, kernel=KERNEL_AUTO) -> Options:
     o = Options()
-    o.precision, o.scatter, o.accumulate, o.block_threads = int(precision), int(scatter), int(accumulate), int(block_threads)
+    o.precision, o.scatter, o.accumulate = int(precision), int(scatter), int(accumulate)
+    o.block_threads, o.kernel = int(block_threads), int(kernel)
     return o
 
 
 def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP64, scatter=ATOMIC,
-             accumulate=False, block_threads=0, values=None, rhs=None, stream=None):
+             accumulate=False, block_threads=0, kernel=KERNEL_AUTO, values=None, rhs=None, stream=None):
     """Launch nsa_assemble on the stream (default: torch's current stream); returns (values, rhs)
     as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given)."""
     if values is None or rhs is None:
         values, rhs = mesh.alloc_outputs(vel.device)
-    o = make_options(precision, scatter, accumulate, block_threads)
+    o = make_options(precision, scatter, accumulate, block_threads, kernel)
     _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
                                _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
     return values, rhs

@@ -27,10 +27,10 @@ def need_gpu():
         pytest.skip("no GPU")
 
 
-def gpu_assemble(mesh, m, precision, scatter, vel=None, **kw):
+def gpu_assemble(mesh, m, precision, scatter, kernel=nsa.KERNEL_AUTO, vel=None, **kw):
     v = torch.from_numpy(m.velocity if vel is None else vel).cuda()
     values, rhs = nsa.assemble(mesh, v, kw.pop("rho", m.rho), kw.pop("mu", m.mu), kw.pop("dt", m.dt),
-                               precision=precision, scatter=scatter, **kw)
+                               precision=precision, scatter=scatter, kernel=kernel, **kw)
     torch.cuda.synchronize()
     return values.cpu().numpy(), rhs.cpu().numpy()
 
@@ -39,18 +39,24 @@ def tol_of(precision):
     return TOL_FP64 if precision == nsa.FP64 else TOL_MIXED
 
 
-@pytest.mark.parametrize("cfg", ["cube8", "cube7_perm", "cube5_rcm", "cube3"])
-@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"{'fp64' if m[0] == 0 else 'mixed'}-{'atomic' if m[1] == 0 else 'colour'}")
-def test_small_meshes(cfg, mode):
-    m = {"cube8": inputs.config_small,
+SMALL = {"cube8": inputs.config_small,
          "cube7_perm": lambda: inputs.make_mesh(7, jitter=True, permute=True, velocity="vortex", seed=17),
          "cube5_rcm": lambda: inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=18),
-         "cube3": lambda: inputs.make_mesh(3, jitter=True, velocity="uniform", seed=19, rho=1.7, mu=3e-2, dt=2e-3)}[cfg]()
-    say(f"[parity] {cfg} nelem={m.nelem} mode={mode}")
+         "cube3": lambda: inputs.make_mesh(3, jitter=True, velocity="uniform", seed=19, rho=1.7, mu=3e-2, dt=2e-3)}
+KERNELS = [("direct", nsa.KERNEL_DIRECT, None), ("tiled64", nsa.KERNEL_TILED, 64),
+           ("tiled512", nsa.KERNEL_TILED, 512), ("tiled1150", nsa.KERNEL_TILED, 1150)]
+
+
+@pytest.mark.parametrize("cfg", list(SMALL))
+@pytest.mark.parametrize("kern", KERNELS, ids=lambda k: k[0])
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"{'fp64' if m[0] == 0 else 'mixed'}-{'atomic' if m[1] == 0 else 'colour'}")
+def test_small_meshes(cfg, kern, mode):
+    m = SMALL[cfg]()
+    say(f"[parity] {cfg} nelem={m.nelem} kernel={kern[0]} mode={mode}")
     ref_v, ref_r = oracle.assemble(m)
-    mesh = nsa.Mesh.from_inputs(m).upload()
-    v, r = gpu_assemble(mesh, m, *mode)
-    assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"{cfg} {mode}")
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=kern[2]).upload()
+    v, r = gpu_assemble(mesh, m, *mode, kernel=kern[1])
+    assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"{cfg} {kern[0]} {mode}")
 
 
 def test_degenerate_parameters():
@@ -60,7 +66,7 @@ def test_degenerate_parameters():
     for rho, mu, dt, vel in ((1.0, 0.0, 1e-2, np.zeros_like(m.velocity)), (2.0, 1e-3, 1e6, m.velocity),
                              (0.5, 1e-1, 1e-9, m.velocity), (1.0, 1e-3, 1e-2, np.zeros_like(m.velocity))):
         ref_v, ref_r = oracle.assemble(m, rho=rho, mu=mu, dt=dt, velocity=vel)
-        for mode in MODES:
+        for mode in MODES + [(p, s_, nsa.KERNEL_DIRECT) for p, s_ in MODES]:
             v, r = gpu_assemble(mesh, m, *mode, vel=vel, rho=rho, mu=mu, dt=dt)
             err = class_errors(v, ref_v, r, ref_r)
             for k, e in err.items():
@@ -78,23 +84,27 @@ def test_accumulate():
     values, rhs = mesh.alloc_outputs()
     values.fill_(1.0)
     rhs.fill_(-2.0)
-    for scatter in (nsa.ATOMIC, nsa.COLOUR):
-        values.fill_(1.0)
-        rhs.fill_(-2.0)
-        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=scatter, accumulate=True, values=values, rhs=rhs)
-        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=scatter, accumulate=True, values=values, rhs=rhs)
-        torch.cuda.synchronize()
-        assert_parity(values.cpu().numpy() - 1.0, 2 * ref_v, rhs.cpu().numpy() + 2.0, 2 * ref_r, 1e-12)
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+        for scatter in (nsa.ATOMIC, nsa.COLOUR):
+            values.fill_(1.0)
+            rhs.fill_(-2.0)
+            for _ in range(2):
+                nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=scatter, accumulate=True, values=values, rhs=rhs,
+                             kernel=kernel)
+            torch.cuda.synchronize()
+            assert_parity(values.cpu().numpy() - 1.0, 2 * ref_v, rhs.cpu().numpy() + 2.0, 2 * ref_r, 1e-12,
+                          f"accumulate kernel={kernel} scatter={scatter}")
 
 
 def test_colour_path_bit_reproducible():
     m = inputs.make_mesh(12, jitter=True, permute=True, velocity="vortex", seed=25)
     mesh = nsa.Mesh.from_inputs(m).upload()
-    for prec in (nsa.FP64, nsa.MIXED):
-        v0, r0 = gpu_assemble(mesh, m, prec, nsa.COLOUR)
-        for _ in range(9):
-            v, r = gpu_assemble(mesh, m, prec, nsa.COLOUR)
-            assert np.array_equal(v, v0) and np.array_equal(r, r0)
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+        for prec in (nsa.FP64, nsa.MIXED):
+            v0, r0 = gpu_assemble(mesh, m, prec, nsa.COLOUR, kernel=kernel)
+            for _ in range(9):
+                v, r = gpu_assemble(mesh, m, prec, nsa.COLOUR, kernel=kernel)
+                assert np.array_equal(v, v0) and np.array_equal(r, r0)
 
 
 def test_empty_and_tiny():
@@ -108,9 +118,10 @@ def test_empty_and_tiny():
     m = inputs.make_mesh(1, jitter=True, seed=26)           # 6 tets
     ref_v, ref_r = oracle.assemble(m)
     mesh = nsa.Mesh.from_inputs(m).upload()
-    for mode in MODES:
-        v, r = gpu_assemble(mesh, m, *mode)
-        assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"one hex {mode}")
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+        for mode in MODES:
+            v, r = gpu_assemble(mesh, m, *mode, kernel=kernel)
+            assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"one hex {mode} kernel={kernel}")
 
 
 @pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
@@ -123,8 +134,34 @@ def test_cube64_full(scatter):
     mesh = nsa.Mesh.from_inputs(m).upload()
     bptr, bcol, emap = mesh.pattern()
     assert np.array_equal(bptr, pat[0]) and np.array_equal(bcol, pat[1]) and np.array_equal(emap, pat[2])
-    for prec in (nsa.FP64, nsa.MIXED):
-        say(f"[parity] cube64 precision={prec} scatter={scatter}")
-        v, r = gpu_assemble(mesh, m, prec, scatter)
-        err = assert_parity(v, ref_v, r, ref_r, tol_of(prec), f"cube64 {prec} {scatter}")
-        say(f"[parity] cube64 errors {err}")
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+        for prec in (nsa.FP64, nsa.MIXED):
+            say(f"[parity] cube64 kernel={kernel} precision={prec} scatter={scatter}")
+            v, r = gpu_assemble(mesh, m, prec, scatter, kernel=kernel)
+            err = assert_parity(v, ref_v, r, ref_r, tol_of(prec), f"cube64 {prec} {scatter} kernel={kernel}")
+            say(f"[parity] cube64 errors {err}")
+
+
+@pytest.mark.parametrize("precision", [nsa.FP64, nsa.MIXED])
+def test_cube128_sampled(precision):
+    """The 128^3 workload (12,582,912 tets) in the launch configuration the benchmark times
+    (tiled kernel, 512-block tiles, atomic scatter): sampled rows against the oracle computed row by
+    row, plus the colour path on the same rows."""
+    m = inputs.config_128()
+    say(f"[parity] cube128 nelem={m.nelem} precision={precision}")
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512).upload()
+    rng = np.random.default_rng(128)
+    rows = np.unique(np.concatenate([rng.choice(m.npoin, 190, replace=False), [0, 1, m.npoin - 2, m.npoin - 1]]))
+    cols, deg, ov, orr = oracle.assemble_rows(m, rows, maxdeg=64)
+    bptr, bcol, _ = mesh.pattern()
+    for scatter in (nsa.ATOMIC, nsa.COLOUR):
+        v, r = gpu_assemble(mesh, m, precision, scatter, kernel=nsa.KERNEL_TILED)
+        got, ref = [], []
+        for s, i in enumerate(rows):
+            lo, hi = bptr[i], bptr[i + 1]
+            assert np.array_equal(bcol[lo:hi], cols[s, :deg[s]]), f"pattern row {i}"
+            got.append(v[lo:hi])
+            ref.append(ov[s, :deg[s]])
+        err = assert_parity(np.concatenate(got), np.concatenate(ref), r[rows], orr, tol_of(precision),
+                            f"cube128 sampled precision={precision} scatter={scatter}")
+        say(f"[parity] cube128 sampled errors {err}")
