@@ -116,7 +116,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
     ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto"])
-    ap.add_argument("--tile-blocks", type=int, default=512)
+    ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
+    ap.add_argument("--tile-blocks-colour", type=int, default=256, help="tile size of the colour-mode plan")
     ap.add_argument("--no-baseline-fp64", action="store_true", help="skip timing the FP64 kernel beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
@@ -149,11 +150,11 @@ def main():
     t0 = time.perf_counter()
     m = make_workload(args.workload)
     log(f"workload {args.workload}: {m.nelem} tets, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=args.tile_blocks)
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=args.tile_blocks, tile_blocks_colour=args.tile_blocks_colour)
     mesh.upload("cuda:0")
     info = mesh.info
-    log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles} tile_elems/nelem="
-        f"{info.tile_elems / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes}")
+    log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} tile_elems/nelem="
+        f"{info.tile_elems[scat] / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes[scat]}")
     vel = torch.from_numpy(m.velocity).to("cuda:0")
     values, rhs = mesh.alloc_outputs("cuda:0")
     stream = torch.cuda.current_stream()
@@ -177,8 +178,10 @@ def main():
     nbytes = algorithmic_bytes(m.nelem, m.npoin, info.nnzb)
     launch_ms = statistics.fmean(per)
     achieved = nbytes / (launch_ms / 1e3) / 1e9
-    kname = f"k_tiled<{'float' if prec == nsa.MIXED else 'double'},{'colour' if scat == nsa.COLOUR else 'atomic'}>"
-    key = f"{kname}@{args.workload}/tile{args.tile_blocks}"
+    nthreads = info.tile_threads[scat]
+    kname = f"k_tiled<{'float' if prec == nsa.MIXED else 'double'},{nthreads}>"
+    tb = args.tile_blocks if scat == nsa.ATOMIC else args.tile_blocks_colour
+    key = f"{kname}@{args.workload}/tile{tb}"
     traffic = traffic_for(key, nbytes) if kern == nsa.KERNEL_TILED else None
     line = {
         "metric": "elements assembled/s",
@@ -195,7 +198,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {m.name}", "nelem": m.nelem, "npoin": m.npoin,
                    "nnzb": info.nnzb, "precision": args.precision, "scatter": args.scatter,
-                   "kernel": args.kernel, "tile_blocks": args.tile_blocks, "rho": m.rho, "mu": m.mu, "dt": m.dt},
+                   "kernel": args.kernel, "tile_blocks": tb, "rho": m.rho, "mu": m.mu, "dt": m.dt},
         "hbm_GBs": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,

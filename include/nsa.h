@@ -57,17 +57,20 @@ typedef int32_t nsa_status;
 #define NSA_FP64 0             /* everything in FP64 */
 #define NSA_MIXED 1            /* Jacobian, inverse, volume and length in FP64; element integration
                                   in FP32; global accumulation in FP64 */
-/* scatter */
-#define NSA_ATOMIC 0           /* FP64 atomic adds into the global arrays */
-#define NSA_COLOUR 1           /* element colouring: elements of one colour share no node and add
-                                  with plain load-add-store; deterministic, bit-reproducible */
+/* scatter: how contributions that target the same block are combined */
+#define NSA_ATOMIC 0           /* FP64 atomic adds from concurrent threads (throughput mode; the
+                                  order of the additions, hence the last bits, may vary by run) */
+#define NSA_COLOUR 1           /* deterministic, bit-reproducible: the tiled kernel processes each
+                                  tile's elements in tile-colour order inside a single wavefront
+                                  (elements of one colour share no owned node); the direct kernel
+                                  runs one global colour class at a time with plain load-add-store */
 
 /* kernel family */
 #define NSA_KERNEL_AUTO 0      /* the row-tiled kernel when the mesh allows it, else the direct one */
 #define NSA_KERNEL_TILED 1     /* row tiles: each workgroup owns contiguous block rows, reduces the
                                   contributions to them in LDS and writes every block once */
 #define NSA_KERNEL_DIRECT 2    /* element per lane, scattering straight into the global arrays
-                                  (zero-fill first unless accumulating) */
+                                  (zero-fill first unless accumulating); reference implementation */
 
 typedef struct nsa_options {
     int32_t precision;         /* NSA_FP64 or NSA_MIXED */
@@ -75,7 +78,8 @@ typedef struct nsa_options {
     int32_t accumulate;        /* 0: values/rhs are overwritten; 1: contributions are added to
                                   what the arrays hold (the inout semantics of Listing 2) */
     int32_t block_threads;     /* threads per workgroup, 0 = default; direct kernel: 64..256 in
-                                  steps of 64; tiled kernel: 128 or 256 (other values mean 256) */
+                                  steps of 64; tiled atomic mode: 64, 128 or 256 (default 256);
+                                  ignored by the tiled colour mode (one wavefront per tile) */
     int32_t kernel;            /* NSA_KERNEL_AUTO, NSA_KERNEL_TILED or NSA_KERNEL_DIRECT */
     int32_t reserved[3];       /* must be zero */
 } nsa_options;
@@ -86,12 +90,13 @@ typedef struct nsa_mesh_info {
     int32_t uploaded;          /* 1 once nsa_mesh_upload succeeded */
     size_t ws_bytes;           /* device workspace nsa_mesh_upload needs */
     int64_t max_row_blocks;    /* largest row degree of the block pattern */
-    int64_t ntiles;            /* row tiles of the tiled kernel (0 if the mesh cannot use it) */
-    int64_t tile_elems;        /* sum over tiles of the elements each tile evaluates */
-    int32_t tile_blocks;       /* accumulator capacity of a tile, in 4x4 blocks */
-    int32_t tile_max_colours;  /* largest number of tile-local colours */
-    int32_t tile_lds_bytes;    /* LDS a workgroup of the tiled kernel uses */
-    int32_t reserved;
+    /* row-tile plans of the tiled kernel, indexed by scatter mode (NSA_ATOMIC, NSA_COLOUR) */
+    int64_t ntiles[2];         /* number of tiles (0 if the mesh cannot use the tiled kernel) */
+    int64_t tile_elems[2];     /* sum over tiles of the elements each tile evaluates */
+    int32_t tile_blocks[2];    /* requested tile size (LDS budget tile_blocks * 160 bytes) */
+    int32_t tile_threads[2];   /* workgroup size of the plan */
+    int32_t tile_max_colours[2]; /* largest number of tile-local colours */
+    int32_t tile_lds_bytes[2]; /* LDS a workgroup uses (largest tile) */
 } nsa_mesh_info;
 
 typedef struct nsa_mesh nsa_mesh; /* opaque */
@@ -131,11 +136,13 @@ nsa_status nsa_pattern_fill(int64_t npoin, int64_t nelem, const int32_t *lnods, 
  * device data layout. nelem may be 0. */
 nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
                            nsa_mesh **out);
-/* Re-plan the row tiles of the tiled kernel with at most tile_blocks 4x4 blocks per tile (64 to
- * 1150; LDS use is about 128 bytes per block). Tiles are contiguous row ranges; a tile's elements are
+/* Re-plan the row tiles the tiled kernel uses for one scatter mode. A tile is a contiguous range of
+ * block rows whose LDS footprint (136 bytes per block, 44 per row, 48 per touched node) stays within
+ * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB). A tile's elements are
  * every element with a node in it, coloured so that elements of one tile colour share no owned
- * node. Must be called before nsa_mesh_upload (NSA_ESTATE after). Default: 512. */
-nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t tile_blocks);
+ * node. Defaults: 512 (NSA_ATOMIC, 256-thread workgroups) and 256 (NSA_COLOUR, one wavefront per
+ * tile). Must be called before nsa_mesh_upload (NSA_ESTATE after). */
+nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks);
 nsa_status nsa_mesh_destroy(nsa_mesh *m);
 nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info);
 /* Copy the block pattern out (host arrays of the sizes given by nsa_mesh_get_info: bptr
@@ -145,23 +152,18 @@ nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol,
 /* Colour classes: colour_ptr host int32 [ncolours+1], colour_elems host int32 [nelem] (element ids
  * grouped by colour, ascending inside a colour). Either may be NULL. */
 nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems);
-/* Row-tile plan of the tiled kernel (host arrays sized from nsa_mesh_get_info; any may be NULL):
- * tile_row int32 [ntiles+1] (tile t owns rows tile_row[t] .. tile_row[t+1]-1), tile_eptr int64
- * [ntiles+1] (offsets into the element lists), elems_atomic / elems_colour int32 [tile_elems] (the
- * elements of each tile in the atomic-mode order: owned-row count descending, then tile colour, then
- * id; and in the colour-mode order: tile colour, owned-row count descending, id), tile_cptr int32 [ntiles+1] and
- * ccnt int32 [tile_cptr[ntiles]] (colour k of tile t spans positions ccnt[tile_cptr[t]+k] ..
- * ccnt[tile_cptr[t]+k+1]-1 of that tile's colour-order list). NSA_EUNSUPPORTED if ntiles == 0. */
-nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems_atomic,
-                              int32_t *elems_colour, int32_t *tile_cptr, int32_t *ccnt);
-/* Per-tile node tables and element records of the tiled kernel: tile_nptr int64 [ntiles+1],
- * tile_nodes int32 [tile_nptr[ntiles]] (the owned rows of tile t first, as local ids 0 .. nrows-1,
- * then the other nodes its elements touch, ascending), rec_atomic / rec_colour 24 bytes per tile
- * element in the order of elems_atomic / elems_colour: uint16 local node ids[4] (owned nodes first),
- * then uint8 ranks[4][4] where ranks[k][b] is the position of column node b inside the row of the
- * k-th owned node (zero for rows the tile does not own). Any pointer may be NULL. */
-nsa_status nsa_mesh_get_tile_records(const nsa_mesh *m, int64_t *tile_nptr, int32_t *tile_nodes, uint8_t *rec_atomic,
-                                     uint8_t *rec_colour);
+/* Row-tile plan of one scatter mode (host arrays sized from nsa_mesh_get_info with k = scatter; any
+ * may be NULL): tile_row int32 [ntiles+1] (tile t owns rows tile_row[t] .. tile_row[t+1]-1),
+ * tile_eptr int64 [ntiles+1] (record offsets), elems int32 [tile_elems] (element of each record),
+ * colours int32 [tile_elems] (its tile-local colour), tile_nptr int64 [ntiles+1] and tile_nodes
+ * int32 [tile_nptr[ntiles]] (the owned rows of tile t first, as local ids 0 .. nrows-1, then the
+ * other nodes its elements touch, ascending), records 24 bytes per record: uint16 local node
+ * ids[4] (owned nodes first), then uint8 ranks[4][4] where ranks[k][b] is the position of column
+ * node b inside the row of the k-th owned node (zero for rows the tile does not own).
+ * NSA_EUNSUPPORTED if the mesh has no plan for that mode. */
+nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
+                              int32_t *elems, int32_t *colours, int64_t *tile_nptr, int32_t *tile_nodes,
+                              uint8_t *records);
 /* Make the mesh device-resident: copies the connectivity, coordinates, block maps, colour lists and
  * schedules into ws (device, at least info.ws_bytes bytes, 256-byte aligned, caller-owned and kept
  * alive while the mesh is used). Synchronous: returns after the copies completed on the stream. */

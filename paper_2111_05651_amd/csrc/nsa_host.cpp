@@ -177,8 +177,11 @@ nsa_status colour_elements(nsa_mesh *m) {
     return NSA_OK;
 }
 
-constexpr int32_t kDefaultTileBlocks = 512;
-constexpr int32_t kMaxTileBlocks = 1150;
+// Default tile plans: the throughput plan uses 512-block tiles (80 KB of LDS, two workgroups of
+// four wavefronts per CU); the deterministic plan uses 256-block tiles owned by one wavefront each.
+constexpr int32_t kDefaultTileBlocks[2] = {512, 256};
+constexpr int32_t kPlanThreads[2] = {256, 64};
+constexpr int32_t kMaxTileBlocks = 1024;
 constexpr int32_t kMaxTileRows = 256;
 constexpr int64_t kMaxTileLds = 160 * 1024;  // LDS one workgroup may use on gfx950
 
@@ -201,35 +204,27 @@ int parallel_chunks(int64_t n, F f) {
 }
 
 // Row tiles for the tiled kernel (see nsa_internal.h). A tile is a contiguous row range whose LDS
-// footprint (block image, RHS rows, row offsets, node table) stays within tile_blocks * 160 bytes, so
-// that two workgroups fit in a CU. Per tile: the nodes its elements touch (the owned rows first, as
-// local ids 0 .. nrows-1, then the other nodes ascending), and one 24-byte record per element with
-// its local node ids (owned nodes first) and the in-row ranks of its owned rows, in the atomic-mode
-// and the colour-mode orders.
-nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
-    m->tile_blocks = tile_blocks;
-    m->tiled_ok = false;
-    std::vector<int32_t>().swap(m->tile_row);
-    std::vector<int64_t>().swap(m->tile_eptr);
-    std::vector<int32_t>().swap(m->tile_elems_a);
-    std::vector<int32_t>().swap(m->tile_elems_c);
-    std::vector<int32_t>().swap(m->tile_cptr);
-    std::vector<int32_t>().swap(m->tile_ccnt);
-    std::vector<int64_t>().swap(m->tile_nptr);
-    std::vector<int32_t>().swap(m->tile_nodes);
-    std::vector<nsa::TileRec>().swap(m->tile_rec_a);
-    std::vector<nsa::TileRec>().swap(m->tile_rec_c);
-    m->cap_blocks = m->cap_rows = m->cap_nodes = m->tile_max_colours = 0;
-    m->tile_lds = 0;
+// footprint (block image, RHS rows, row offsets, node table) stays within tile_blocks * 160 bytes.
+// Per tile: the nodes its elements touch (the owned rows first, as local ids 0 .. nrows-1, then the
+// other nodes ascending), a greedy colouring of its elements (elements of one tile colour share no
+// owned node), and one 24-byte record per element with its local node ids (owned nodes first) and
+// the in-row ranks of its owned rows. Record order: for the throughput plan, owned-row count
+// descending (the lanes of a wavefront run the same number of row iterations) then colour (lanes
+// of one instruction rarely add into the same LDS block); for the deterministic plan, colour, then
+// owned-row count descending.
+nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads, bool colour_first) {
+    P = nsa::TilePlan();
+    P.tile_blocks = tile_blocks;
+    P.threads = threads;
     // uint8 in-row ranks and uint16 local node ids bound what the tiled kernel can address
     if (m->max_row_blocks > 256 || m->npoin == 0) return NSA_OK;
     const int64_t np = m->npoin;
-    const int64_t budget = std::max<int64_t>(std::min<int64_t>((int64_t)tile_blocks * 160, kMaxTileLds),
-                                             nsa::tile_lds_bytes((int32_t)m->max_row_blocks, 1, (int32_t)m->max_row_blocks));
-    if (budget > kMaxTileLds) return NSA_OK;  // a single row would not fit in LDS
+    const int64_t one_row = (int64_t)nsa::tile_lds_bytes((int32_t)m->max_row_blocks, 1, (int32_t)m->max_row_blocks);
+    if (one_row > kMaxTileLds) return NSA_OK;  // a single row would not fit in LDS
+    const int64_t budget = std::max<int64_t>(std::min<int64_t>((int64_t)tile_blocks * 160, kMaxTileLds), one_row);
     // grow tiles row by row; the touched nodes of a tile are the columns of its rows
     std::vector<int32_t> stamp(np, -1);
-    m->tile_row.push_back(0);
+    P.row.push_back(0);
     int32_t tid = 0;
     for (int64_t r0 = 0; r0 < np; tid++) {
         int64_t r1 = r0, nodes = 0;
@@ -237,31 +232,30 @@ nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
             int64_t add = 0;
             for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) add += stamp[m->bcol[k]] != tid;
             const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
-            const size_t need = nsa::tile_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
-            if (r1 > r0 && ((int64_t)need > budget || r1 + 1 - r0 > kMaxTileRows)) break;
+            const int64_t need = (int64_t)nsa::tile_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
+            if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows)) break;
             for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
             nodes += add;
             r1++;
         }
         if (nodes > 65535) return fail(NSA_EUNSUPPORTED, "a tile touches more than 65535 nodes");
-        m->tile_row.push_back((int32_t)r1);
-        m->cap_rows = std::max<int32_t>(m->cap_rows, (int32_t)(r1 - r0));
-        m->cap_blocks = std::max<int32_t>(m->cap_blocks, (int32_t)(m->bptr[r1] - m->bptr[r0]));
-        m->cap_nodes = std::max<int32_t>(m->cap_nodes, (int32_t)nodes);
-        m->tile_lds = std::max<int64_t>(m->tile_lds, (int64_t)nsa::tile_lds_bytes(
-            (int32_t)(m->bptr[r1] - m->bptr[r0]), (int32_t)(r1 - r0), (int32_t)nodes));
+        P.row.push_back((int32_t)r1);
+        P.cap_rows = std::max<int32_t>(P.cap_rows, (int32_t)(r1 - r0));
+        P.cap_blocks = std::max<int32_t>(P.cap_blocks, (int32_t)(m->bptr[r1] - m->bptr[r0]));
+        P.cap_nodes = std::max<int32_t>(P.cap_nodes, (int32_t)nodes);
+        P.lds = std::max<int64_t>(P.lds, (int64_t)nsa::tile_lds_bytes((int32_t)(m->bptr[r1] - m->bptr[r0]),
+                                                                      (int32_t)(r1 - r0), (int32_t)nodes));
         r0 = r1;
     }
     std::vector<int32_t>().swap(stamp);
-    const int64_t nt = (int64_t)m->tile_row.size() - 1;
+    const int64_t nt = (int64_t)P.row.size() - 1;
     std::vector<int64_t> n2e_ptr;
     std::vector<int32_t> n2e;
     node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
     struct Out {
-        std::vector<int32_t> ea, ec, ccnt, nodes;
-        std::vector<nsa::TileRec> ra, rc;
-        std::vector<int64_t> cnt, ncnt;  // per tile element / node counts
-        std::vector<int32_t> ncol;       // per tile colour count
+        std::vector<int32_t> els, col, nodes;
+        std::vector<nsa::TileRec> recs;
+        std::vector<int64_t> cnt, ncnt;  // per tile record / node counts
         int32_t maxcol = 0;
         bool too_many = false;
     };
@@ -271,7 +265,7 @@ nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
         std::vector<int32_t> els, col, nown, idx, other;
         std::vector<uint64_t> mask;
         for (int64_t t = tb; t < te; t++) {
-            const int32_t r0 = m->tile_row[t], r1 = m->tile_row[t + 1], nr = r1 - r0;
+            const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
             els.clear();
             for (int32_t i = r0; i < r1; i++) els.insert(els.end(), n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
             std::sort(els.begin(), els.end());
@@ -293,10 +287,10 @@ nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
                 if (g >= r0 && g < r1) return g - r0;
                 return nr + (int32_t)(std::lower_bound(other.begin(), other.end(), g) - other.begin());
             };
+            // greedy colouring in element order: conflicts are shared owned nodes
             col.assign(ne, 0);
             nown.assign(ne, 0);
             mask.assign(2 * (size_t)nr, 0);
-            int32_t ncol = 0;
             for (size_t j = 0; j < ne; j++) {
                 const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
                 uint64_t f0 = 0, f1 = 0;
@@ -321,9 +315,17 @@ nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
                     if (l >= 0 && l < nr) mask[2 * l + (c >> 6)] |= 1ull << (c & 63);
                 }
                 col[j] = c;
-                ncol = std::max(ncol, c + 1);
+                o.maxcol = std::max(o.maxcol, c + 1);
             }
-            auto record = [&](size_t j) {
+            idx.resize(ne);
+            for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
+            std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+                if (colour_first && col[x] != col[y]) return col[x] < col[y];
+                if (nown[x] != nown[y]) return nown[x] > nown[y];
+                if (col[x] != col[y]) return col[x] < col[y];
+                return els[x] < els[y];
+            });
+            for (int32_t j : idx) {
                 const int64_t e = els[j];
                 const int32_t *ln = &m->lnods[4 * e];
                 int ord[4], k = 0;
@@ -335,63 +337,34 @@ nsa_status build_tiles(nsa_mesh *m, int32_t tile_blocks) {
                 for (int q = 0; q < 4; q++) r.loc[q] = (uint16_t)local(ln[ord[q]]);
                 for (int q = 0; q < nown[j]; q++) {
                     const int64_t rs = m->bptr[ln[ord[q]]];
-                    for (int b = 0; b < 4; b++)
-                        r.rank[q][b] = (uint8_t)(m->emap[16 * e + 4 * ord[q] + ord[b]] - rs);
+                    for (int b = 0; b < 4; b++) r.rank[q][b] = (uint8_t)(m->emap[16 * e + 4 * ord[q] + ord[b]] - rs);
                 }
-                return r;
-            };
-            idx.resize(ne);
-            for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
-            // atomic order: owned-row count descending (lanes of a wavefront run the same number of
-            // row iterations), then colour, so that neighbouring lanes rarely add into the same LDS
-            // block in one instruction
-            std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-                if (nown[x] != nown[y]) return nown[x] > nown[y];
-                if (col[x] != col[y]) return col[x] < col[y];
-                return els[x] < els[y];
-            });
-            for (int32_t j : idx) {
-                o.ea.push_back(els[j]);
-                o.ra.push_back(record(j));
+                o.els.push_back((int32_t)e);
+                o.col.push_back(col[j]);
+                o.recs.push_back(r);
             }
-            // colour order: colour, then owned-row count descending, then id
-            std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return col[x] < col[y]; });
-            std::vector<int32_t> cc(ncol + 1, 0);
-            for (int32_t j : idx) {
-                o.ec.push_back(els[j]);
-                o.rc.push_back(record(j));
-                cc[col[j] + 1]++;
-            }
-            for (int c = 0; c < ncol; c++) cc[c + 1] += cc[c];
-            o.ccnt.insert(o.ccnt.end(), cc.begin(), cc.end());
             o.cnt.push_back((int64_t)ne);
-            o.ncol.push_back(ncol);
-            o.maxcol = std::max(o.maxcol, ncol);
         }
     });
     for (int i = 0; i < used; i++)
         if (outs[i].too_many) return fail(NSA_EUNSUPPORTED, "a tile needs more than 128 colours");
-    m->tile_eptr.assign(1, 0);
-    m->tile_cptr.assign(1, 0);
-    m->tile_nptr.assign(1, 0);
+    P.eptr.assign(1, 0);
+    P.nptr.assign(1, 0);
     for (int i = 0; i < used; i++) {
         Out &o = outs[i];
         for (size_t k = 0; k < o.cnt.size(); k++) {
-            m->tile_eptr.push_back(m->tile_eptr.back() + o.cnt[k]);
-            m->tile_cptr.push_back(m->tile_cptr.back() + o.ncol[k] + 1);
-            m->tile_nptr.push_back(m->tile_nptr.back() + o.ncnt[k]);
+            P.eptr.push_back(P.eptr.back() + o.cnt[k]);
+            P.nptr.push_back(P.nptr.back() + o.ncnt[k]);
         }
-        m->tile_elems_a.insert(m->tile_elems_a.end(), o.ea.begin(), o.ea.end());
-        m->tile_elems_c.insert(m->tile_elems_c.end(), o.ec.begin(), o.ec.end());
-        m->tile_ccnt.insert(m->tile_ccnt.end(), o.ccnt.begin(), o.ccnt.end());
-        m->tile_nodes.insert(m->tile_nodes.end(), o.nodes.begin(), o.nodes.end());
-        m->tile_rec_a.insert(m->tile_rec_a.end(), o.ra.begin(), o.ra.end());
-        m->tile_rec_c.insert(m->tile_rec_c.end(), o.rc.begin(), o.rc.end());
-        m->tile_max_colours = std::max(m->tile_max_colours, o.maxcol);
+        P.elems.insert(P.elems.end(), o.els.begin(), o.els.end());
+        P.colour.insert(P.colour.end(), o.col.begin(), o.col.end());
+        P.nodes.insert(P.nodes.end(), o.nodes.begin(), o.nodes.end());
+        P.recs.insert(P.recs.end(), o.recs.begin(), o.recs.end());
+        P.max_colours = std::max(P.max_colours, o.maxcol);
         o = Out();
     }
-    if ((int64_t)m->tile_eptr.size() != nt + 1) return fail(NSA_EUNSUPPORTED, "tile plan inconsistent");
-    m->tiled_ok = true;
+    if ((int64_t)P.eptr.size() != nt + 1) return fail(NSA_EUNSUPPORTED, "tile plan inconsistent");
+    P.ok = true;
     return NSA_OK;
 }
 
@@ -410,18 +383,25 @@ void plan_layout(nsa_mesh *m) {
     take(m->r_emap, 16 * ne * sizeof(int32_t));
     take(m->r_ln_c, 4 * ne * sizeof(int32_t));
     take(m->r_emap_c, 16 * ne * sizeof(int32_t));
-    const bool t = m->tiled_ok;
+    const bool t = m->plan[0].ok || m->plan[1].ok;
     take(m->r_coord4, t ? 4 * np * sizeof(double) : 0);
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
-    take(m->r_tile_row, t ? m->tile_row.size() * sizeof(int32_t) : 0);
-    take(m->r_tile_eptr, t ? m->tile_eptr.size() * sizeof(int64_t) : 0);
-    take(m->r_tile_cptr, t ? m->tile_cptr.size() * sizeof(int32_t) : 0);
-    take(m->r_tile_ccnt, t ? m->tile_ccnt.size() * sizeof(int32_t) : 0);
-    take(m->r_tile_nptr, t ? m->tile_nptr.size() * sizeof(int64_t) : 0);
-    take(m->r_tile_nodes, t ? m->tile_nodes.size() * sizeof(int32_t) : 0);
-    take(m->r_tile_rec_a, t ? m->tile_rec_a.size() * sizeof(nsa::TileRec) : 0);
-    take(m->r_tile_rec_c, t ? m->tile_rec_c.size() * sizeof(nsa::TileRec) : 0);
+    for (nsa::TilePlan &P : m->plan) {
+        take(P.r_row, P.ok ? P.row.size() * sizeof(int32_t) : 0);
+        take(P.r_eptr, P.ok ? P.eptr.size() * sizeof(int64_t) : 0);
+        take(P.r_nptr, P.ok ? P.nptr.size() * sizeof(int64_t) : 0);
+        take(P.r_nodes, P.ok ? P.nodes.size() * sizeof(int32_t) : 0);
+        take(P.r_recs, P.ok ? P.recs.size() * sizeof(nsa::TileRec) : 0);
+    }
     m->ws_bytes = std::max<size_t>(off, 256);
+}
+
+nsa_status build_plans(nsa_mesh *m) {
+    for (int k = 0; k < 2; k++) {
+        nsa_status st = build_tiles(m, m->plan[k], kDefaultTileBlocks[k], kPlanThreads[k], k == NSA_COLOUR);
+        if (st) return st;
+    }
+    return NSA_OK;
 }
 
 nsa_status hip_check(hipError_t e, const char *what) {
@@ -540,7 +520,7 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
         m->emap.resize(16 * (size_t)nelem);
         fill_emap(nelem, lnods, m->bptr.data(), m->bcol.data(), m->emap.data());
         st = colour_elements(m);
-        if (!st) st = build_tiles(m, kDefaultTileBlocks);
+        if (!st) st = build_plans(m);
         if (st) {
             delete m;
             return st;
@@ -554,13 +534,14 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
     return ok();
 }
 
-nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t tile_blocks) {
+nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_set_tiling: null mesh");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
     if (tile_blocks < 64 || tile_blocks > kMaxTileBlocks)
         return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d]", tile_blocks, kMaxTileBlocks);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tiling after upload");
     try {
-        nsa_status st = build_tiles(m, tile_blocks);
+        nsa_status st = build_tiles(m, m->plan[scatter], tile_blocks, kPlanThreads[scatter], scatter == NSA_COLOUR);
         if (st) return st;
         plan_layout(m);
     } catch (const std::bad_alloc &) {
@@ -583,12 +564,15 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
     info->uploaded = m->ws != nullptr;
     info->ws_bytes = m->ws_bytes;
     info->max_row_blocks = m->max_row_blocks;
-    info->ntiles = m->tiled_ok ? (int64_t)m->tile_row.size() - 1 : 0;
-    info->tile_elems = m->tiled_ok ? m->tile_eptr.back() : 0;
-    info->tile_blocks = m->tile_blocks;
-    info->tile_max_colours = m->tile_max_colours;
-    info->tile_lds_bytes = m->tiled_ok ? (int32_t)m->tile_lds : 0;
-    info->reserved = 0;
+    for (int k = 0; k < 2; k++) {
+        const nsa::TilePlan &P = m->plan[k];
+        info->ntiles[k] = P.ntiles();
+        info->tile_elems[k] = P.nrec();
+        info->tile_blocks[k] = P.tile_blocks;
+        info->tile_threads[k] = P.threads;
+        info->tile_max_colours[k] = P.max_colours;
+        info->tile_lds_bytes[k] = P.ok ? (int32_t)P.lds : 0;
+    }
     return ok();
 }
 
@@ -609,29 +593,21 @@ nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_
     return ok();
 }
 
-nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems_atomic,
-                              int32_t *elems_colour, int32_t *tile_cptr, int32_t *ccnt) {
+nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
+                              int32_t *elems, int32_t *colours, int64_t *tile_nptr, int32_t *tile_nodes,
+                              uint8_t *records) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_tiles: null mesh");
-    if (!m->tiled_ok) return fail(NSA_EUNSUPPORTED, "no tile plan for this mesh");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    const nsa::TilePlan &P = m->plan[scatter];
+    if (!P.ok) return fail(NSA_EUNSUPPORTED, "no tile plan for this mesh");
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
-    if (tile_row) std::copy(m->tile_row.begin(), m->tile_row.end(), tile_row);
-    if (tile_eptr) std::copy(m->tile_eptr.begin(), m->tile_eptr.end(), tile_eptr);
-    if (elems_atomic) std::copy(m->tile_elems_a.begin(), m->tile_elems_a.end(), elems_atomic);
-    if (elems_colour) std::copy(m->tile_elems_c.begin(), m->tile_elems_c.end(), elems_colour);
-    if (tile_cptr) std::copy(m->tile_cptr.begin(), m->tile_cptr.end(), tile_cptr);
-    if (ccnt) std::copy(m->tile_ccnt.begin(), m->tile_ccnt.end(), ccnt);
-    return ok();
-}
-
-nsa_status nsa_mesh_get_tile_records(const nsa_mesh *m, int64_t *tile_nptr, int32_t *tile_nodes, uint8_t *rec_atomic,
-                                     uint8_t *rec_colour) {
-    if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_tile_records: null mesh");
-    if (!m->tiled_ok) return fail(NSA_EUNSUPPORTED, "no tile plan for this mesh");
-    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
-    if (tile_nptr) std::copy(m->tile_nptr.begin(), m->tile_nptr.end(), tile_nptr);
-    if (tile_nodes) std::copy(m->tile_nodes.begin(), m->tile_nodes.end(), tile_nodes);
-    if (rec_atomic) std::memcpy(rec_atomic, m->tile_rec_a.data(), m->tile_rec_a.size() * sizeof(nsa::TileRec));
-    if (rec_colour) std::memcpy(rec_colour, m->tile_rec_c.data(), m->tile_rec_c.size() * sizeof(nsa::TileRec));
+    if (tile_row) std::copy(P.row.begin(), P.row.end(), tile_row);
+    if (tile_eptr) std::copy(P.eptr.begin(), P.eptr.end(), tile_eptr);
+    if (elems) std::copy(P.elems.begin(), P.elems.end(), elems);
+    if (colours) std::copy(P.colour.begin(), P.colour.end(), colours);
+    if (tile_nptr) std::copy(P.nptr.begin(), P.nptr.end(), tile_nptr);
+    if (tile_nodes) std::copy(P.nodes.begin(), P.nodes.end(), tile_nodes);
+    if (records) std::memcpy(records, P.recs.data(), P.recs.size() * sizeof(nsa::TileRec));
     return ok();
 }
 
@@ -658,7 +634,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         for (int64_t i = 0; i < np; i++)
             for (int d = 0; d < 3; d++) co[d * np + i] = m->coord[3 * i + d];
         std::vector<double> co4;
-        if (m->tiled_ok) {
+        if (m->plan[0].ok || m->plan[1].ok) {
             co4.assign(4 * (size_t)np, 0.0);
             for (int64_t i = 0; i < np; i++)
                 for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
@@ -666,13 +642,14 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         char *w = (char *)ws;
         nsa_status st;
         struct Up { const nsa::Region &r; const void *src; };
+        const nsa::TilePlan &P0 = m->plan[0], &P1 = m->plan[1];
         const Up ups[] = {{m->r_ln, ln.data()}, {m->r_coord, co.data()}, {m->r_emap, em.data()},
                           {m->r_ln_c, lnc.data()}, {m->r_emap_c, emc.data()},
                           {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
-                          {m->r_tile_row, m->tile_row.data()}, {m->r_tile_eptr, m->tile_eptr.data()},
-                          {m->r_tile_cptr, m->tile_cptr.data()}, {m->r_tile_ccnt, m->tile_ccnt.data()},
-                          {m->r_tile_nptr, m->tile_nptr.data()}, {m->r_tile_nodes, m->tile_nodes.data()},
-                          {m->r_tile_rec_a, m->tile_rec_a.data()}, {m->r_tile_rec_c, m->tile_rec_c.data()}};
+                          {P0.r_row, P0.row.data()}, {P0.r_eptr, P0.eptr.data()}, {P0.r_nptr, P0.nptr.data()},
+                          {P0.r_nodes, P0.nodes.data()}, {P0.r_recs, P0.recs.data()},
+                          {P1.r_row, P1.row.data()}, {P1.r_eptr, P1.eptr.data()}, {P1.r_nptr, P1.nptr.data()},
+                          {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()}};
         for (const Up &u : ups) {
             if (!u.r.bytes) continue;
             st = hip_check(hipMemcpyAsync(w + u.r.off, u.src, u.r.bytes, hipMemcpyHostToDevice, s),
@@ -700,12 +677,12 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m) {
     std::vector<int32_t>().swap(m->bcol);
     std::vector<int32_t>().swap(m->emap);
     std::vector<int32_t>().swap(m->colour_elems);
-    std::vector<int32_t>().swap(m->tile_elems_a);
-    std::vector<int32_t>().swap(m->tile_elems_c);
-    std::vector<int32_t>().swap(m->tile_ccnt);
-    std::vector<int32_t>().swap(m->tile_nodes);
-    std::vector<nsa::TileRec>().swap(m->tile_rec_a);
-    std::vector<nsa::TileRec>().swap(m->tile_rec_c);
+    for (nsa::TilePlan &P : m->plan) {
+        std::vector<int32_t>().swap(P.elems);
+        std::vector<int32_t>().swap(P.colour);
+        std::vector<int32_t>().swap(P.nodes);
+        std::vector<nsa::TileRec>().swap(P.recs);
+    }
     m->host_released = true;
     return ok();
 }
@@ -725,7 +702,8 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
     if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED && o.kernel != NSA_KERNEL_DIRECT)
         return fail(NSA_EINVAL, "unknown kernel %d", o.kernel);
-    if (o.kernel == NSA_KERNEL_TILED && !m->tiled_ok)
+    const nsa::TilePlan &P = m->plan[o.scatter];
+    if (o.kernel == NSA_KERNEL_TILED && !P.ok)
         return fail(NSA_EUNSUPPORTED, "this mesh cannot use the tiled kernel (row degree > 256 or no plan)");
     int threads = o.block_threads ? o.block_threads : 256;
     if (threads < 64 || threads > 256 || threads % 64)
@@ -744,21 +722,15 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         return fail(NSA_EINVAL, "mesh uploaded on device %d, current device is %d", m->device, dev);
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.precision == NSA_MIXED;
-    if (o.kernel != NSA_KERNEL_DIRECT && m->tiled_ok) {
+    if (o.kernel != NSA_KERNEL_DIRECT && P.ok) {
         nsa::TileArgs t;
-        t.ntiles = (int64_t)m->tile_row.size() - 1;
-        t.npoin = m->npoin;
-        t.cap_blocks = m->cap_blocks;
-        t.cap_rows = m->cap_rows;
-        t.tile_row = (const int32_t *)(m->ws + m->r_tile_row.off);
-        t.tile_eptr = (const int64_t *)(m->ws + m->r_tile_eptr.off);
-        t.rec = (const uint2 *)(m->ws + (o.scatter == NSA_COLOUR ? m->r_tile_rec_c.off : m->r_tile_rec_a.off));
-        t.tile_cptr = (const int32_t *)(m->ws + m->r_tile_cptr.off);
-        t.ccnt = (const int32_t *)(m->ws + m->r_tile_ccnt.off);
-        t.tile_nptr = (const int64_t *)(m->ws + m->r_tile_nptr.off);
-        t.tile_nodes = (const int32_t *)(m->ws + m->r_tile_nodes.off);
-        t.cap_nodes = m->cap_nodes;
-        t.lds_bytes = m->tile_lds;
+        t.ntiles = P.ntiles();
+        t.lds_bytes = P.lds;
+        t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
+        t.tile_eptr = (const int64_t *)(m->ws + P.r_eptr.off);
+        t.rec = (const uint2 *)(m->ws + P.r_recs.off);
+        t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
+        t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
         t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
         t.coord = (const double4 *)(m->ws + m->r_coord4.off);
         t.vel = vel;
@@ -766,12 +738,12 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         t.mu = mu;
         t.dt = dt;
         t.accumulate = o.accumulate;
-        t.threads = (o.block_threads == 128) ? 128 : 256;
+        // the deterministic plan relies on one wavefront per tile; the throughput plan accepts a
+        // workgroup-size override for tuning
+        t.threads = (o.scatter == NSA_COLOUR || o.block_threads == 0) ? P.threads : o.block_threads;
         t.values = values;
         t.rhs = rhs;
-        const nsa::TileKern k = o.scatter == NSA_COLOUR ? (mixed ? nsa::TileKern::ColourMixed : nsa::TileKern::ColourF64)
-                                                        : (mixed ? nsa::TileKern::AtomicMixed : nsa::TileKern::AtomicF64);
-        st = hip_check(nsa::launch_tiled(k, t, s), "assemble (tiled)");
+        st = hip_check(nsa::launch_tiled(mixed ? nsa::TileKern::Mixed : nsa::TileKern::F64, t, s), "assemble (tiled)");
         return st ? st : ok();
     }
     if (!o.accumulate) {

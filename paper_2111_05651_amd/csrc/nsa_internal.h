@@ -18,8 +18,8 @@ struct Region {
     size_t off = 0, bytes = 0;
 };
 
-// Arguments of one element-assembly launch. Element data are SoA with leading dimension ld:
-// ln[a*ld + e] (a = 0..3) and emap[k*ld + e] (k = 4a+b, 0..15); coordinates are SoA
+// Arguments of one direct (element-per-lane) launch. Element data are SoA with leading dimension
+// ld: ln[a*ld + e] (a = 0..3) and emap[k*ld + e] (k = 4a+b, 0..15); coordinates are SoA
 // coord[d*npoin + node]; the velocity is the caller's AoS vel[3*node + d].
 struct AsmArgs {
     int64_t e0 = 0, e1 = 0;      // element range [e0, e1) of the SoA arrays
@@ -39,14 +39,12 @@ enum class Kern { AtomicF64, AtomicMixed, ColourF64, ColourMixed };
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s);
 hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s);
 
-// Row tiles: tile t owns the contiguous block rows [tile_row[t], tile_row[t+1]) and therefore the
-// contiguous blocks [bptr[r0], bptr[r1]). Its nodes tile_nodes[tile_nptr[t] .. tile_nptr[t+1]) are the
-// owned rows (local ids 0 .. nrows-1) followed by every other node its elements touch. Its elements
-// (every element with at least one node in the tile) are described by 24-byte records
-// rec[tile_eptr[t] .. tile_eptr[t+1]): local node ids with the owned nodes first, and for the k-th
-// owned node the in-row ranks of the four columns (in the same order). In the colour order, colour k
-// of tile t spans records tile_eptr[t] + ccnt[tile_cptr[t] + k] .. tile_eptr[t] + ccnt[tile_cptr[t] + k + 1];
-// elements of one tile colour share no owned node.
+// Row tiles: tile t owns the contiguous block rows [row[t], row[t+1]) and therefore the contiguous
+// blocks [bptr[r0], bptr[r1]). Its nodes tile_nodes[nptr[t] .. nptr[t+1]) are the owned rows (local
+// ids 0 .. nrows-1) followed by every other node its elements touch. Its elements (every element
+// with at least one node in the tile) are described by 24-byte records rec[eptr[t] .. eptr[t+1]):
+// local node ids with the owned nodes first, and for the k-th owned node the in-row ranks of the
+// four columns (in the same order).
 struct TileRec {
     uint16_t loc[4];
     uint8_t rank[4][4];
@@ -55,16 +53,10 @@ static_assert(sizeof(TileRec) == 24, "tile record layout");
 
 struct TileArgs {
     int64_t ntiles = 0;
-    int64_t npoin = 0;
-    int32_t cap_blocks = 0;      // LDS block image capacity (blocks)
-    int32_t cap_rows = 0;        // LDS RHS / row-offset capacity (rows)
-    int32_t cap_nodes = 0;       // LDS node table capacity (nodes)
-    int64_t lds_bytes = 0;       // dynamic LDS per workgroup (the largest tile's layout)
+    int64_t lds_bytes = 0;               // dynamic LDS per workgroup (the largest tile's layout)
     const int32_t *tile_row = nullptr;   // [ntiles+1]
     const int64_t *tile_eptr = nullptr;  // [ntiles+1]
     const uint2 *rec = nullptr;          // [sum] TileRec as 3 x uint2
-    const int32_t *tile_cptr = nullptr;  // [ntiles+1]
-    const int32_t *ccnt = nullptr;       // per tile: ncol+1 offsets
     const int64_t *tile_nptr = nullptr;  // [ntiles+1]
     const int32_t *tile_nodes = nullptr; // [sum]
     const int64_t *bptr = nullptr;       // [npoin+1]
@@ -72,7 +64,7 @@ struct TileArgs {
     const double *vel = nullptr;         // [npoin][3]
     double rho = 1, mu = 0, dt = 1;
     int32_t accumulate = 0;
-    int32_t threads = 256;               // workgroup size: 128 or 256
+    int32_t threads = 256;               // workgroup size: 64, 128 or 256
     double *values = nullptr;
     double *rhs = nullptr;
 };
@@ -82,17 +74,36 @@ struct TileArgs {
 // (x, y, z, u, v, w) at a 16-byte aligned offset, then the int32 row offsets.
 constexpr int kBlkStride = 17;
 constexpr int kRhsStride = 5;
-__host__ __device__ constexpr int64_t lds_racc_off(int32_t cap_blocks) { return (int64_t)kBlkStride * cap_blocks; }
-__host__ __device__ constexpr int64_t lds_nodes_off(int32_t cap_blocks, int32_t cap_rows) {
-    return (lds_racc_off(cap_blocks) + (int64_t)kRhsStride * cap_rows + 1) & ~int64_t(1);
+__host__ __device__ constexpr int64_t lds_racc_off(int32_t nblk) { return (int64_t)kBlkStride * nblk; }
+__host__ __device__ constexpr int64_t lds_nodes_off(int32_t nblk, int32_t nrows) {
+    return (lds_racc_off(nblk) + (int64_t)kRhsStride * nrows + 1) & ~int64_t(1);
 }
-__host__ __device__ constexpr int64_t lds_rowoff_off(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
-    return lds_nodes_off(cap_blocks, cap_rows) + 6 * (int64_t)cap_nodes;
+__host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows, int32_t nnodes) {
+    return lds_nodes_off(nblk, nrows) + 6 * (int64_t)nnodes;
 }
 
-enum class TileKern { AtomicF64, AtomicMixed, ColourF64, ColourMixed };
-size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes);
+enum class TileKern { F64, Mixed };
+size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);
+
+// A row-tile plan for one scatter mode (host copy, then device regions after upload).
+struct TilePlan {
+    int32_t tile_blocks = 0;     // requested tile size: LDS budget tile_blocks * 160 bytes
+    int32_t threads = 256;       // workgroup size the plan is meant for
+    bool ok = false;             // plan exists (the mesh fits the tiled kernel)
+    int32_t cap_blocks = 0, cap_rows = 0, cap_nodes = 0, max_colours = 0;
+    int64_t lds = 0;             // LDS bytes of the largest tile
+    std::vector<int32_t> row;    // [ntiles+1]
+    std::vector<int64_t> eptr;   // [ntiles+1]
+    std::vector<int32_t> elems;  // element ids in record order
+    std::vector<int32_t> colour; // tile-local colour of each record
+    std::vector<int64_t> nptr;   // [ntiles+1]
+    std::vector<int32_t> nodes;
+    std::vector<TileRec> recs;
+    Region r_row, r_eptr, r_nptr, r_nodes, r_recs;
+    int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
+    int64_t nrec() const { return ok ? eptr.back() : 0; }
+};
 
 }  // namespace nsa
 
@@ -109,25 +120,10 @@ struct nsa_mesh {
     std::vector<int32_t> emap;          // [nelem][16]
     std::vector<int32_t> colour_ptr;    // [ncolours+1]
     std::vector<int32_t> colour_elems;  // [nelem]
-    // row tiles (see nsa::TileArgs)
-    int32_t tile_blocks = 0;            // requested accumulator capacity per tile (blocks)
-    int32_t cap_blocks = 0, cap_rows = 0, cap_nodes = 0;
-    int64_t tile_lds = 0;               // LDS bytes of the largest tile
-    std::vector<int32_t> tile_row;      // [ntiles+1]
-    std::vector<int64_t> tile_eptr;     // [ntiles+1]
-    std::vector<int32_t> tile_elems_a;  // atomic order: owned-row count descending, then id
-    std::vector<int32_t> tile_elems_c;  // colour order: colour, owned-row count descending, id
-    std::vector<int32_t> tile_cptr;     // [ntiles+1]
-    std::vector<int32_t> tile_ccnt;
-    std::vector<int64_t> tile_nptr;     // [ntiles+1]
-    std::vector<int32_t> tile_nodes;
-    std::vector<nsa::TileRec> tile_rec_a, tile_rec_c;
-    int32_t tile_max_colours = 0;
+    // row-tile plans: [NSA_ATOMIC] throughput plan, [NSA_COLOUR] deterministic plan
+    nsa::TilePlan plan[2];
     // device layout (offsets into the caller's workspace)
-    nsa::Region r_ln, r_coord, r_emap, r_ln_c, r_emap_c;
-    nsa::Region r_coord4, r_bptr, r_tile_row, r_tile_eptr, r_tile_cptr, r_tile_ccnt, r_tile_nptr, r_tile_nodes,
-        r_tile_rec_a, r_tile_rec_c;
-    bool tiled_ok = false;              // uint8 ranks fit and the plan exists
+    nsa::Region r_ln, r_coord, r_emap, r_ln_c, r_emap_c, r_coord4, r_bptr;
     size_t ws_bytes = 0;
     char *ws = nullptr;                 // device, caller-owned
     int device = -1;

@@ -250,20 +250,20 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 // Row-tiled assembly (the default path).
 //
 // One workgroup owns a tile of contiguous block rows and the contiguous range of blocks they hold.
-// It keeps an FP64 image of those blocks (and of the tile's RHS rows) in LDS, runs every element
-// that touches one of its rows, adds the contributions of the owned rows into the LDS image, and
-// finally writes the image to HBM once, coalesced. No global atomics, no zero-fill pass, and every
-// value line is written exactly once. Elements on a tile boundary are evaluated by each tile they
-// touch; only their owned rows are integrated there.
+// It stages the coordinates and velocities of the nodes its elements touch in LDS, keeps an FP64
+// image of its blocks (and of its RHS rows) in LDS, runs every element that touches one of its rows
+// from a precomputed 24-byte record, adds the contributions of the owned rows into the LDS image
+// with FP64 LDS atomics (ds_add_f64), and finally writes the image to HBM once, coalesced. No
+// global atomics, no zero-fill pass, and every value line is written exactly once. Elements on a
+// tile boundary are evaluated by each tile they touch; only their owned rows are integrated there.
 //
-// Duplicate targets inside a tile are reduced in LDS, either with FP64 LDS atomics (ds_add_f64) in
-// the atomic mode, or in the colour mode by processing the tile's elements colour by colour
-// (elements of one tile colour share no owned node), so every LDS block is updated with a plain
-// read-add-write in a fixed order and the result is bit-reproducible.
-//
-// Inside an element the local nodes are reordered so that the owned ones come first; the plan sorts
-// each tile's elements (inside a colour) by how many rows they own, so the lanes of a wavefront run
-// the same number of row iterations.
+// Two plans use this kernel. The throughput plan gives a tile to a workgroup of four wavefronts;
+// the order in which their LDS atomics land on one block varies from run to run. The deterministic
+// plan gives each (smaller) tile to a single wavefront: every LDS word of the tile is then updated
+// only by that wavefront's instructions, which the LDS executes in issue order, lanes of one
+// instruction in a fixed order, so the sums are bit-reproducible. Its records are ordered by
+// tile-local element colour (elements of one colour share no owned node), so the lanes of one
+// instruction rarely target the same block.
 // ================================================================================================
 namespace {
 
@@ -373,64 +373,81 @@ __device__ __forceinline__ void setup_t(const Geo2 &g, const double Ud[4][3], do
 }
 
 // Row a of the element: RHS (4 values) and the four 4x4 blocks (a, b), each handed to put(b, blk).
+// Per row the coefficients that depend on a only are formed once; a block then costs ~40 operations:
+//   T    = (rho/dt) V/20 (1 + d_ab) + rho V/20 (s_b + d[a][b]) + mu V K_ab
+//          + tau1 rho (rho V/20 (s_a s_b + gram_ab) + (rho/dt) V/20 (s_a + d[b][a]))
+//   uu   = T I + mu V G_b G_a^T + tau2 V G_a G_b^T         (diagonal: G_b[c] (mu V + tau2 V) G_a[c] + T)
+//   up   = -V/4 G_a + tau1 rho V/4 s_a G_b
+//   pu   = V/4 G_b + tau1 G_a (rho V/4 s_b + (rho/dt) V/4)
+//   pp   = tau1 V K_ab
 template <typename R, typename Put>
 __device__ __forceinline__ void element_row(const ElemT<R> &E, int a, R rb[4], Put put) {
-    const R ga0 = E.G[a][0], ga1 = E.G[a][1], ga2 = E.G[a][2], sa = E.s[a];
+    const R ga[3] = {E.G[a][0], E.G[a][1], E.G[a][2]};
+    const R sa = E.s[a];
     // RHS: (rho/dt) int u_c N_a + tau1 rho (rho/dt) int (a.grad N_a) u_c ; PSPG tau1 (rho/dt) V/4 s_a
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const R un = E.v20 * (E.su[c] + E.U[a][c]);
-        const R au = E.v20 * (sa * E.su[c] + E.d[0][a] * E.U[0][c] + E.d[1][a] * E.U[1][c] +
-                              E.d[2][a] * E.U[2][c] + E.d[3][a] * E.U[3][c]);
-        rb[c] = E.rdt * (un + E.t1rho * au);
+        const R un = E.su[c] + E.U[a][c];
+        const R au = sa * E.su[c] + E.d[0][a] * E.U[0][c] + E.d[1][a] * E.U[1][c] + E.d[2][a] * E.U[2][c] +
+                     E.d[3][a] * E.U[3][c];
+        rb[c] = E.rdt * E.v20 * (un + E.t1rho * au);
     }
     rb[3] = E.t1 * E.rdt * E.v4 * sa;
-    const R gm[3] = {E.muV * ga0, E.muV * ga1, E.muV * ga2};
-    const R gt[3] = {E.t2V * ga0, E.t2V * ga1, E.t2V * ga2};
-    const R pa[3] = {-E.v4 * ga0, -E.v4 * ga1, -E.v4 * ga2};
-    const R tg[3] = {E.t1 * ga0, E.t1 * ga1, E.t1 * ga2};
+    R gm[3], gt[3], gmt[3], pa[3], tg[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        gm[c] = E.muV * ga[c];
+        gt[c] = E.t2V * ga[c];
+        gmt[c] = gm[c] + gt[c];
+        pa[c] = -E.v4 * ga[c];
+        tg[c] = E.t1 * ga[c];
+    }
     const R qa = E.t1rho * E.v4 * sa;
-    const R c2sa = E.c2 * sa;
-    const R c3sa = E.c3 * sa;
+    const R tbase = E.Mo + E.c3 * sa;        // a-only part of T
+    const R ksb = E.c1 + E.c2 * sa;          // coefficient of s_b in T
+    const R rv4 = E.rho * E.v4, dv4 = E.rdt * E.v4;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
-        const R gb0 = E.G[b][0], gb1 = E.G[b][1], gb2 = E.G[b][2], sb = E.s[b];
-        const R K = ga0 * gb0 + ga1 * gb1 + ga2 * gb2;
+        const R gb[3] = {E.G[b][0], E.G[b][1], E.G[b][2]};
+        const R sb = E.s[b];
+        const R K = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
         const R gram = E.d[0][a] * E.d[0][b] + E.d[1][a] * E.d[1][b] + E.d[2][a] * E.d[2][b] + E.d[3][a] * E.d[3][b];
-        const R T = (a == b ? E.Md : E.Mo) + E.c1 * (sb + E.d[a][b]) + E.muV * K + c2sa * sb + E.c2 * gram +
-                    c3sa + E.c3 * E.d[b][a];
-        const R gbv[3] = {gb0, gb1, gb2};
+        R T = tbase + ksb * sb + E.c1 * E.d[a][b] + E.c3 * E.d[b][a] + E.c2 * gram + E.muV * K;
+        if (a == b) T += E.Mo;
         R blk[16];
 #pragma unroll
         for (int c = 0; c < 3; c++)
 #pragma unroll
-            for (int cp = 0; cp < 3; cp++) {
-                const R v = gm[cp] * gbv[c] + gt[c] * gbv[cp];
-                blk[4 * c + cp] = (c == cp) ? v + T : v;
-            }
-        const R rbb = E.rho * E.v4 * sb + E.rdt * E.v4;
+            for (int cp = 0; cp < 3; cp++)
+                blk[4 * c + cp] = (c == cp) ? gb[c] * gmt[c] + T : gm[cp] * gb[c] + gt[c] * gb[cp];
+        const R rbb = rv4 * sb + dv4;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            blk[4 * c + 3] = pa[c] + qa * gbv[c];
-            blk[12 + c] = E.v4 * gbv[c] + tg[c] * rbb;
+            blk[4 * c + 3] = pa[c] + qa * gb[c];
+            blk[12 + c] = E.v4 * gb[c] + tg[c] * rbb;
         }
         blk[15] = E.t1V * K;
         put(b, blk);
     }
 }
 
-__device__ __forceinline__ void lds_add(double *p, double v, bool colour) {
-    if (colour)
-        *p += v;
-    else
-        __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // One element of the tile from its record: node data from the LDS node table, owned rows first.
-template <typename R, bool COLOUR>
-__device__ __forceinline__ void tile_element(const TileArgs &A, int64_t p, int nrows, double *acc, double *racc,
+struct Rec {
+    uint2 w0, w1, w2;
+};
+
+__device__ __forceinline__ Rec load_rec(const TileArgs &A, int64_t p) {
+    return Rec{A.rec[3 * p], A.rec[3 * p + 1], A.rec[3 * p + 2]};
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_element(const TileArgs &A, const Rec &rc, int nrows, double *acc, double *racc,
                                              const double *nodes, const int *rowoff) {
-    const uint2 w0 = A.rec[3 * p], w1 = A.rec[3 * p + 1], w2 = A.rec[3 * p + 2];
+    const uint2 w0 = rc.w0, w1 = rc.w1, w2 = rc.w2;
     const int loc[4] = {(int)(w0.x & 0xffffu), (int)(w0.x >> 16), (int)(w0.y & 0xffffu), (int)(w0.y >> 16)};
     const uint32_t rw[4] = {w1.x, w1.y, w2.x, w2.y};
     int nown = 0;
@@ -464,15 +481,15 @@ __device__ __forceinline__ void tile_element(const TileArgs &A, int64_t p, int n
         element_row<R>(E, a, rb, [&](int b, const R *blk) {
             double *q = acc + kBlkStride * slot[b];
 #pragma unroll
-            for (int i = 0; i < 16; i++) lds_add(q + i, (double)blk[i], COLOUR);
+            for (int i = 0; i < 16; i++) lds_add(q + i, (double)blk[i]);
         });
         double *q = racc + kRhsStride * lr;
 #pragma unroll
-        for (int c = 0; c < 4; c++) lds_add(q + c, (double)rb[c], COLOUR);
+        for (int c = 0; c < 4; c++) lds_add(q + c, (double)rb[c]);
     }
 }
 
-template <typename R, bool COLOUR, int NT>
+template <typename R, int NT>
 __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     extern __shared__ double smem[];
     // XCD-aware order: workgroup w runs on XCD w % 8, so give each XCD a contiguous run of tiles
@@ -492,7 +509,11 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     double *racc = smem + lds_racc_off(nblk);
     double *nodes = smem + lds_nodes_off(nblk, nrows);
     int *rowoff = reinterpret_cast<int *>(smem + lds_rowoff_off(nblk, nrows, nnod));
-    for (int i = tid; i < nrows; i += NT) rowoff[i] = (int)(A.bptr[r0 + i] - b0);
+    const int64_t p0 = A.tile_eptr[tile], p1 = A.tile_eptr[tile + 1];
+    // issue the first element record and the node gathers before the LDS clears and the barrier
+    Rec cur{};
+    int64_t p = p0 + tid;
+    if (p < p1) cur = load_rec(A, p);
     for (int i = tid; i < nnod; i += NT) {
         const int64_t gnode = A.tile_nodes[n0 + i];
         const double4 c = A.coord[gnode];
@@ -502,21 +523,22 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
         nd[1] = make_double2(c.z, v[0]);
         nd[2] = make_double2(v[1], v[2]);
     }
-    for (int i = tid; i < kBlkStride * nblk; i += NT) acc[i] = 0.0;
+    for (int i = tid; i < nrows; i += NT) rowoff[i] = (int)(A.bptr[r0 + i] - b0);
+    {
+        double2 *a2 = reinterpret_cast<double2 *>(acc);
+        const int n2 = (kBlkStride * nblk + 1) >> 1;
+        for (int i = tid; i < n2; i += NT) a2[i] = make_double2(0.0, 0.0);
+    }
     for (int i = tid; i < kRhsStride * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();
-    const int64_t p0 = A.tile_eptr[tile];
-    if (!COLOUR) {
-        const int64_t p1 = A.tile_eptr[tile + 1];
-        for (int64_t p = p0 + tid; p < p1; p += NT) tile_element<R, false>(A, p, nrows, acc, racc, nodes, rowoff);
-    } else {
-        const int32_t *cc = A.ccnt + A.tile_cptr[tile];
-        const int ncol = A.tile_cptr[tile + 1] - A.tile_cptr[tile] - 1;
-        for (int c = 0; c < ncol; c++) {
-            for (int64_t p = p0 + cc[c] + tid; p < p0 + cc[c + 1]; p += NT)
-                tile_element<R, true>(A, p, nrows, acc, racc, nodes, rowoff);
-            __syncthreads();
-        }
+    // one record ahead: the next element's record is in flight while this one is integrated
+    while (p < p1) {
+        const int64_t pn = p + NT;
+        Rec nxt{};
+        if (pn < p1) nxt = load_rec(A, pn);
+        tile_element<R>(A, cur, nrows, acc, racc, nodes, rowoff);
+        cur = nxt;
+        p = pn;
     }
     __syncthreads();
     // write the image out: block k, value pair j -> values[(b0 + k) * 16 + 2j]
@@ -551,7 +573,7 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = (size_t)a.lds_bytes;
     const int64_t per = (a.ntiles + 7) / 8;
-    const int nt = a.threads == 128 ? 128 : 256;
+    const int nt = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
     const dim3 grid((unsigned)(8 * per)), block(nt);
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -560,21 +582,10 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(kern, grid, block, lds, s, a);
         return hipGetLastError();
     };
-    if (nt == 128) {
-        switch (k) {
-            case TileKern::AtomicF64: return go(k_tiled<double, false, 128>);
-            case TileKern::AtomicMixed: return go(k_tiled<float, false, 128>);
-            case TileKern::ColourF64: return go(k_tiled<double, true, 128>);
-            case TileKern::ColourMixed: return go(k_tiled<float, true, 128>);
-        }
-    } else {
-        switch (k) {
-            case TileKern::AtomicF64: return go(k_tiled<double, false, 256>);
-            case TileKern::AtomicMixed: return go(k_tiled<float, false, 256>);
-            case TileKern::ColourF64: return go(k_tiled<double, true, 256>);
-            case TileKern::ColourMixed: return go(k_tiled<float, true, 256>);
-        }
-    }
+    const bool mixed = k == TileKern::Mixed;
+    if (nt == 64) return mixed ? go(k_tiled<float, 64>) : go(k_tiled<double, 64>);
+    if (nt == 128) return mixed ? go(k_tiled<float, 128>) : go(k_tiled<double, 128>);
+    if (nt == 256) return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
     return hipErrorInvalidValue;
 }
 

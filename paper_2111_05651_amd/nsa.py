@@ -22,7 +22,7 @@ KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT = 0, 1, 2
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
-           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_tile_records", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
+           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
 
 
 class NsaError(RuntimeError):
@@ -39,8 +39,9 @@ class Options(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [("npoin", C.c_int64), ("nelem", C.c_int64), ("nnzb", C.c_int64), ("ncolours", C.c_int32),
                 ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64),
-                ("ntiles", C.c_int64), ("tile_elems", C.c_int64), ("tile_blocks", C.c_int32),
-                ("tile_max_colours", C.c_int32), ("tile_lds_bytes", C.c_int32), ("reserved", C.c_int32)]
+                ("ntiles", C.c_int64 * 2), ("tile_elems", C.c_int64 * 2), ("tile_blocks", C.c_int32 * 2),
+                ("tile_threads", C.c_int32 * 2), ("tile_max_colours", C.c_int32 * 2),
+                ("tile_lds_bytes", C.c_int32 * 2)]
 
 
 _lib = None
@@ -63,13 +64,12 @@ def load(path: str = LIB_PATH):
     lib.nsa_pattern_count.argtypes = [i64, i64, P, P, P]
     lib.nsa_pattern_fill.argtypes = [i64, i64, P, P, P, P]
     lib.nsa_mesh_create.argtypes = [i64, i64, P, P, C.POINTER(P)]
-    lib.nsa_mesh_set_tiling.argtypes = [P, i32]
+    lib.nsa_mesh_set_tiling.argtypes = [P, i32, i32]
     lib.nsa_mesh_destroy.argtypes = [P]
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
     lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
-    lib.nsa_mesh_get_tiles.argtypes = [P, P, P, P, P, P, P]
-    lib.nsa_mesh_get_tile_records.argtypes = [P, P, P, P, P]
+    lib.nsa_mesh_get_tiles.argtypes = [P, i32, P, P, P, P, P, P, P]
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
     lib.nsa_mesh_release_host.argtypes = [P]
     lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
@@ -119,7 +119,8 @@ def pattern(npoin: int, lnods: np.ndarray):
 class Mesh:
     """A registered mesh (host handle) and, after upload(), its device workspace (a torch tensor)."""
 
-    def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None):
+    def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
+                 tile_blocks_colour: int | None = None):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -130,15 +131,17 @@ class Mesh:
         self._h = h
         self.ws = None
         if tile_blocks is not None:
-            _check(lib.nsa_mesh_set_tiling(h, int(tile_blocks)), "nsa_mesh_set_tiling")
+            _check(lib.nsa_mesh_set_tiling(h, ATOMIC, int(tile_blocks)), "nsa_mesh_set_tiling")
+        if tile_blocks_colour is not None:
+            _check(lib.nsa_mesh_set_tiling(h, COLOUR, int(tile_blocks_colour)), "nsa_mesh_set_tiling")
         self.info = self._info()
 
     @classmethod
-    def from_inputs(cls, m, tile_blocks: int | None = None) -> "Mesh":
-        return cls(m.lnods, m.coord, tile_blocks)
+    def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None) -> "Mesh":
+        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour)
 
-    def set_tiling(self, tile_blocks: int):
-        _check(load().nsa_mesh_set_tiling(self._h, int(tile_blocks)), "nsa_mesh_set_tiling")
+    def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
+        _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")
         self.info = self._info()
 
     def _info(self) -> MeshInfo:
@@ -173,26 +176,22 @@ class Mesh:
         _check(load().nsa_mesh_get_colouring(self._h, _ptr(cptr), _ptr(celems)), "nsa_mesh_get_colouring")
         return cptr, celems
 
-    def tiles(self):
-        """Row-tile plan: dict of tile_row, tile_eptr, elems_atomic, elems_colour, tile_cptr, ccnt."""
+    def tiles(self, scatter: int = ATOMIC):
+        """Row-tile plan of one scatter mode: dict of tile_row, tile_eptr, elems, colours, tile_nptr,
+        tile_nodes and records (structured: loc uint16[4], rank uint8[4][4])."""
         i = self.info
-        out = dict(tile_row=np.zeros(i.ntiles + 1, np.int32), tile_eptr=np.zeros(i.ntiles + 1, np.int64),
-                   elems_atomic=np.zeros(i.tile_elems, np.int32), elems_colour=np.zeros(i.tile_elems, np.int32),
-                   tile_cptr=np.zeros(i.ntiles + 1, np.int32))
-        _check(load().nsa_mesh_get_tiles(self._h, _ptr(out["tile_row"]), _ptr(out["tile_eptr"]), None, None,
-                                          _ptr(out["tile_cptr"]), None), "nsa_mesh_get_tiles")
-        out["ccnt"] = np.zeros(int(out["tile_cptr"][-1]), np.int32)
-        _check(load().nsa_mesh_get_tiles(self._h, None, None, _ptr(out["elems_atomic"]), _ptr(out["elems_colour"]),
-                                          None, _ptr(out["ccnt"])), "nsa_mesh_get_tiles")
-        nptr = np.zeros(i.ntiles + 1, np.int64)
-        _check(load().nsa_mesh_get_tile_records(self._h, _ptr(nptr), None, None, None), "nsa_mesh_get_tile_records")
+        nt, ne = i.ntiles[scatter], i.tile_elems[scatter]
         rec_dt = np.dtype([("loc", np.uint16, (4,)), ("rank", np.uint8, (4, 4))])
-        out["tile_nptr"] = nptr
-        out["tile_nodes"] = np.zeros(int(nptr[-1]), np.int32)
-        out["rec_atomic"] = np.zeros(i.tile_elems, rec_dt)
-        out["rec_colour"] = np.zeros(i.tile_elems, rec_dt)
-        _check(load().nsa_mesh_get_tile_records(self._h, None, _ptr(out["tile_nodes"]), _ptr(out["rec_atomic"]),
-                                                _ptr(out["rec_colour"])), "nsa_mesh_get_tile_records")
+        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_eptr=np.zeros(nt + 1, np.int64),
+                   elems=np.zeros(ne, np.int32), colours=np.zeros(ne, np.int32), tile_nptr=np.zeros(nt + 1, np.int64),
+                   records=np.zeros(ne, rec_dt))
+        lib = load()
+        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), None, None, None, None, _ptr(out["tile_nptr"]), None,
+                                      None), "nsa_mesh_get_tiles")
+        out["tile_nodes"] = np.zeros(int(out["tile_nptr"][-1]), np.int32)
+        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), _ptr(out["tile_row"]), _ptr(out["tile_eptr"]),
+                                      _ptr(out["elems"]), _ptr(out["colours"]), None, _ptr(out["tile_nodes"]),
+                                      _ptr(out["records"])), "nsa_mesh_get_tiles")
         return out
 
     def upload(self, device="cuda", stream=None):

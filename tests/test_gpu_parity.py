@@ -44,7 +44,7 @@ SMALL = {"cube8": inputs.config_small,
          "cube5_rcm": lambda: inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=18),
          "cube3": lambda: inputs.make_mesh(3, jitter=True, velocity="uniform", seed=19, rho=1.7, mu=3e-2, dt=2e-3)}
 KERNELS = [("direct", nsa.KERNEL_DIRECT, None), ("tiled64", nsa.KERNEL_TILED, 64),
-           ("tiled512", nsa.KERNEL_TILED, 512), ("tiled1150", nsa.KERNEL_TILED, 1150)]
+           ("tiled_default", nsa.KERNEL_TILED, None), ("tiled1024", nsa.KERNEL_TILED, 1024)]
 
 
 @pytest.mark.parametrize("cfg", list(SMALL))
@@ -54,7 +54,7 @@ def test_small_meshes(cfg, kern, mode):
     m = SMALL[cfg]()
     say(f"[parity] {cfg} nelem={m.nelem} kernel={kern[0]} mode={mode}")
     ref_v, ref_r = oracle.assemble(m)
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=kern[2]).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=kern[2], tile_blocks_colour=kern[2]).upload()
     v, r = gpu_assemble(mesh, m, *mode, kernel=kern[1])
     assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"{cfg} {kern[0]} {mode}")
 
@@ -105,6 +105,28 @@ def test_colour_path_bit_reproducible():
             for _ in range(9):
                 v, r = gpu_assemble(mesh, m, prec, nsa.COLOUR, kernel=kernel)
                 assert np.array_equal(v, v0) and np.array_equal(r, r0)
+
+
+def test_colour_path_reproducible_under_load():
+    """Bit-identical results while another stream keeps the GPU busy (different wave interleavings),
+    and across different launch streams."""
+    m = inputs.make_mesh(20, jitter=True, permute=True, velocity="vortex", seed=27)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    vel = torch.from_numpy(m.velocity).cuda()
+    v0, r0 = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=nsa.COLOUR)
+    torch.cuda.synchronize()
+    v0, r0 = v0.cpu().numpy(), r0.cpu().numpy()
+    side = torch.cuda.Stream()
+    a = torch.randn(2048, 2048, device="cuda")
+    for it in range(12):
+        with torch.cuda.stream(side):
+            for _ in range(4):
+                a = (a @ a).tanh_()
+        s = torch.cuda.Stream() if it % 2 else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            v, r = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=nsa.COLOUR, stream=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), v0) and np.array_equal(r.cpu().numpy(), r0), f"run {it}"
 
 
 def test_empty_and_tiny():

@@ -117,89 +117,92 @@ def test_isolated_nodes_match_oracle(lib):
     assert mb[11] == mb[10]
 
 
-def check_tile_plan(m, mesh, lds_limit=160 * 1024):
-    """Every index the tiled kernel derives from the plan stays inside its buffers."""
+def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
+    """Every index the tiled kernel derives from the plan stays inside its buffers, and the record
+    order is the one the mode relies on."""
     info = mesh.info
-    t = mesh.tiles()
+    t = mesh.tiles(scatter)
     bptr, bcol, emap = mesh.pattern()
     tr, te = t["tile_row"], t["tile_eptr"]
     assert tr[0] == 0 and tr[-1] == m.npoin and np.all(np.diff(tr) > 0)
     nblk = bptr[tr[1:]] - bptr[tr[:-1]]
     nrows = np.diff(tr)
-    assert info.tile_lds_bytes <= lds_limit
     nnod = np.diff(t["tile_nptr"])
     need = [((17 * b + 5 * r + 1) // 2 * 2 + 6 * n) * 8 + 4 * r for b, r, n in zip(nblk, nrows, nnod)]
-    assert info.tile_lds_bytes == max(need), "LDS allocation must cover the largest tile's layout"
+    assert info.tile_lds_bytes[scatter] == max(need) <= lds_limit, "LDS allocation must cover the largest tile"
+    assert max(need) <= max(info.tile_blocks[scatter] * 160, need[int(np.argmax(nblk))])
     ranks = emap - bptr[m.lnods][:, :, None]
-    deg = (bptr[1:] - bptr[:-1])[m.lnods]
-    assert np.all(ranks >= 0) and np.all(ranks < deg[:, :, None]) and ranks.max() < 256
+    assert ranks.max() < 256
     n2e = [[] for _ in range(m.npoin)]
     for e, nodes in enumerate(m.lnods):
         for a in nodes:
             n2e[a].append(e)
     for k in range(len(tr) - 1):
         r0, r1 = tr[k], tr[k + 1]
-        ea = t["elems_atomic"][te[k]:te[k + 1]]
-        ec = t["elems_colour"][te[k]:te[k + 1]]
+        nr = r1 - r0
+        els = t["elems"][te[k]:te[k + 1]]
+        cols = t["colours"][te[k]:te[k + 1]]
+        recs = t["records"][te[k]:te[k + 1]]
         want = sorted({e for i in range(r0, r1) for e in n2e[i]})
-        assert sorted(ea) == want and sorted(ec) == want
-        own = ((m.lnods[ea] >= r0) & (m.lnods[ea] < r1)).sum(axis=1)
-        assert np.all(np.diff(own) <= 0), "atomic order must be by owned-row count, descending"
-        cc = t["ccnt"][t["tile_cptr"][k]:t["tile_cptr"][k + 1]]
-        assert cc[0] == 0 and cc[-1] == len(ec) and np.all(np.diff(cc) >= 0)
-        for c in range(len(cc) - 1):
-            nodes = m.lnods[ec[cc[c]:cc[c + 1]]].ravel()
+        assert sorted(els) == want
+        own = ((m.lnods[els] >= r0) & (m.lnods[els] < r1)).sum(axis=1)
+        if scatter == nsa.ATOMIC:
+            assert np.all(np.diff(own) <= 0), "throughput order: owned-row count descending"
+        else:
+            assert np.all(np.diff(cols) >= 0), "deterministic order: tile colour ascending"
+        for c in np.unique(cols):
+            nodes = m.lnods[els[cols == c]].ravel()
             owned = nodes[(nodes >= r0) & (nodes < r1)]
             assert np.unique(owned).size == owned.size, f"tile {k} colour {c} shares an owned node"
-        # slots of owned rows stay inside the tile's block range
-        for e in ea:
-            for a in range(4):
-                if r0 <= m.lnods[e, a] < r1:
-                    slots = emap[e, a] - bptr[r0]
-                    assert np.all(slots >= 0) and np.all(slots < nblk[k])
         # node table and records: what the kernel indexes with them
         nodes = t["tile_nodes"][t["tile_nptr"][k]:t["tile_nptr"][k + 1]]
-        nr = r1 - r0
         assert np.array_equal(nodes[:nr], np.arange(r0, r1))
         assert np.all(np.diff(nodes[nr:]) > 0) and not np.any((nodes[nr:] >= r0) & (nodes[nr:] < r1))
-        assert set(nodes.tolist()) == set(m.lnods[ea].ravel().tolist())
-        for order, els in (("rec_atomic", ea), ("rec_colour", ec)):
-            recs = t[order][te[k]:te[k + 1]]
-            for e, rec in zip(els, recs):
-                loc = rec["loc"].astype(np.int64)
-                assert np.all(loc < nodes.size)
-                g = nodes[loc]
-                assert sorted(g.tolist()) == sorted(m.lnods[e].tolist())
-                own = loc < nr
-                nown = int(own.sum())
-                assert np.all(own[:nown]) and not np.any(own[nown:]), "owned nodes must come first"
-                for q in range(nown):
-                    row = g[q]
-                    for b in range(4):
-                        rank = int(rec["rank"][q, b])
-                        assert bptr[row] + rank < bptr[row + 1] and bcol[bptr[row] + rank] == g[b]
-                        assert 0 <= bptr[row] - bptr[r0] + rank < nblk[k]
+        assert set(nodes.tolist()) == set(m.lnods[els].ravel().tolist())
         assert nodes.size <= 65535
+        for e, rec in zip(els, recs):
+            loc = rec["loc"].astype(np.int64)
+            assert np.all(loc < nodes.size)
+            g = nodes[loc]
+            assert sorted(g.tolist()) == sorted(m.lnods[e].tolist())
+            ow = loc < nr
+            nown = int(ow.sum())
+            assert np.all(ow[:nown]) and not np.any(ow[nown:]), "owned nodes must come first"
+            for q in range(nown):
+                row = g[q]
+                for b in range(4):
+                    rank = int(rec["rank"][q, b])
+                    assert bptr[row] + rank < bptr[row + 1] and bcol[bptr[row] + rank] == g[b]
+                    assert 0 <= bptr[row] - bptr[r0] + rank < nblk[k]
 
 
-@pytest.mark.parametrize("tile_blocks", [64, 200, 512, 1150])
-def test_tile_plan_in_bounds(lib, tile_blocks):
+@pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
+@pytest.mark.parametrize("tile_blocks", [64, 200, 512, 1024])
+def test_tile_plan_in_bounds(lib, scatter, tile_blocks):
     m = inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=31)
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=tile_blocks)
-    assert mesh.info.ntiles >= 1 and mesh.info.tile_blocks == tile_blocks
-    check_tile_plan(m, mesh)
+    mesh = nsa.Mesh(m.lnods, m.coord)
+    mesh.set_tiling(tile_blocks, scatter)
+    assert mesh.info.ntiles[scatter] >= 1 and mesh.info.tile_blocks[scatter] == tile_blocks
+    check_tile_plan(m, mesh, scatter)
 
 
-def test_tile_plan_random_numbering(lib):
+def test_tile_plan_defaults(lib):
     m = inputs.make_mesh(4, jitter=True, permute=True, seed=32)
-    check_tile_plan(m, nsa.Mesh.from_inputs(m))
+    mesh = nsa.Mesh.from_inputs(m)
+    assert list(mesh.info.tile_blocks) == [512, 256] and list(mesh.info.tile_threads) == [256, 64]
+    for scatter in (nsa.ATOMIC, nsa.COLOUR):
+        check_tile_plan(m, mesh, scatter)
     m1 = inputs.make_mesh(1, seed=33)
-    check_tile_plan(m1, nsa.Mesh.from_inputs(m1, tile_blocks=64))
+    mesh1 = nsa.Mesh.from_inputs(m1, tile_blocks=64, tile_blocks_colour=64)
+    for scatter in (nsa.ATOMIC, nsa.COLOUR):
+        check_tile_plan(m1, mesh1, scatter)
 
 
 def test_tiling_arguments(lib):
     m = inputs.make_mesh(2, seed=34)
     mesh = nsa.Mesh.from_inputs(m)
-    for bad in (0, 63, 1151):
+    for bad in (0, 63, 1025):
         with pytest.raises(nsa.NsaError):
             mesh.set_tiling(bad)
+    with pytest.raises(nsa.NsaError):
+        mesh.set_tiling(256, scatter=7)
