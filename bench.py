@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--tile-blocks-colour", type=int, default=256, help="tile size of the colour-mode plan")
     ap.add_argument("--no-baseline-fp64", action="store_true", help="skip timing the FP64 kernel beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="elements for the CPU baseline (0 = the whole mesh)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="instead: time a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -206,7 +206,7 @@ def main():
         "fp64_baseline": fp64,
     }
     if not args.no_cpu_baseline:
-        ns = min(args.cpu_sample, m.nelem)
+        ns = min(args.cpu_sample, m.nelem) if args.cpu_sample > 0 else m.nelem
         log(f"cpu baseline: oracle on {ns} elements ...")
         line["cpu_baseline"] = cpu_baseline(m, ns)
     print(json.dumps(line), flush=True)
