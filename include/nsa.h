@@ -141,7 +141,10 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
  * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB). A tile's elements are
  * every element with a node in it, coloured so that elements of one tile colour share no owned
  * node. Defaults: 512 (NSA_ATOMIC, 256-thread workgroups) and 256 (NSA_COLOUR, one wavefront per
- * tile). Must be called before nsa_mesh_upload (NSA_ESTATE after). */
+ * tile); tile_blocks = 0 drops the plan of that mode (the tiled kernel then refuses the mode and
+ * NSA_KERNEL_AUTO falls back to the direct kernel). Plans are built on first need
+ * (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be called before nsa_mesh_upload
+ * (NSA_ESTATE after). */
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks);
 nsa_status nsa_mesh_destroy(nsa_mesh *m);
 nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info);
@@ -183,6 +186,38 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m);
  * Asynchronous on stream. Errors: NSA_EINVAL, NSA_ESTATE (not uploaded), NSA_EHIP (launch). */
 nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
                         const nsa_options *opt, double *values, double *rhs, void *stream);
+
+/* ---- batched form ------------------------------------------------------------------------------ */
+
+typedef struct nsa_batch nsa_batch; /* opaque */
+
+/* Many uploaded meshes (uneven sizes) assembled by one persistent launch of the tiled kernel: a
+ * grid of resident workgroups walks the concatenated tile lists of all meshes (each mesh's tiles
+ * contiguous, every XCD a contiguous slice). Every mesh must be uploaded on the current device and
+ * have a tile plan for `scatter` (NSA_EUNSUPPORTED otherwise). The meshes must outlive the batch. */
+nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out);
+nsa_status nsa_batch_destroy(nsa_batch *b);
+/* Device workspace the batch needs, total tiles and elements, LDS per workgroup (any may be NULL). */
+nsa_status nsa_batch_get_info(const nsa_batch *b, size_t *ws_bytes, int64_t *ntiles, int64_t *nelem,
+                              int32_t *lds_bytes);
+/* Copy the work table into ws (device, >= ws_bytes, 256-byte aligned, caller-owned, kept alive while
+ * the batch is used). Synchronous. */
+nsa_status nsa_batch_upload(nsa_batch *b, void *ws, size_t ws_bytes, void *stream);
+/* Per-mesh inputs and outputs (arrays of nmesh entries, in the order of nsa_batch_create): device
+ * velocity [npoin][3], rho > 0, mu >= 0, dt > 0, device values [nnzb][4][4] and rhs [npoin][4]
+ * (16-byte aligned); accumulate as in nsa_options. Stream-ordered copy of the per-mesh descriptors
+ * into the batch workspace (waits for the previous call's copy to finish reading its host staging).
+ * Not to be captured in a graph: call it before launching or replaying one. */
+nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const double *rho, const double *mu,
+                                const double *dt, double *const *values, double *const *rhs, int32_t accumulate,
+                                void *stream);
+/* One persistent launch over every tile of every mesh of the batch. opt->scatter must equal the
+ * batch's mode; opt->kernel must not be NSA_KERNEL_DIRECT; opt->block_threads may pick 128 or 256
+ * threads per workgroup in the atomic mode. grid_wgs: workgroups of the persistent
+ * grid (rounded up to a multiple of 8; 0 = 2 per CU, 4 per CU for the one-wavefront colour plan).
+ * No allocation, no memset, no host synchronisation: the call may be captured in a HIP graph, and a
+ * captured graph replays with whatever inputs the last nsa_batch_set_inputs installed. */
+nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream);
 
 #ifdef __cplusplus
 }

@@ -396,11 +396,26 @@ void plan_layout(nsa_mesh *m) {
     m->ws_bytes = std::max<size_t>(off, 256);
 }
 
-nsa_status build_plans(nsa_mesh *m) {
-    for (int k = 0; k < 2; k++) {
-        nsa_status st = build_tiles(m, m->plan[k], kDefaultTileBlocks[k], kPlanThreads[k], k == NSA_COLOUR);
-        if (st) return st;
+// Build the requested plans (once) and the device layout. Logically const: called from the read
+// accessors of a mesh.
+nsa_status ensure_plans(const nsa_mesh *cm) {
+    nsa_mesh *m = const_cast<nsa_mesh *>(cm);
+    std::lock_guard<std::mutex> g(m->plan_mu);
+    if (m->planned) return NSA_OK;
+    try {
+        for (int k = 0; k < 2; k++) {
+            if (m->want_blocks[k] > 0) {
+                nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], kPlanThreads[k], k == NSA_COLOUR);
+                if (st) return st;
+            } else {
+                m->plan[k] = nsa::TilePlan();
+            }
+        }
+        plan_layout(m);
+    } catch (const std::bad_alloc &) {
+        return fail(NSA_ENOMEM, "tile planning: host allocation failed");
     }
+    m->planned = true;
     return NSA_OK;
 }
 
@@ -520,12 +535,12 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
         m->emap.resize(16 * (size_t)nelem);
         fill_emap(nelem, lnods, m->bptr.data(), m->bcol.data(), m->emap.data());
         st = colour_elements(m);
-        if (!st) st = build_plans(m);
+        m->want_blocks[0] = kDefaultTileBlocks[0];
+        m->want_blocks[1] = kDefaultTileBlocks[1];
         if (st) {
             delete m;
             return st;
         }
-        plan_layout(m);
     } catch (const std::bad_alloc &) {
         delete m;
         return fail(NSA_ENOMEM, "nsa_mesh_create: host allocation failed");
@@ -537,15 +552,13 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_set_tiling: null mesh");
     if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
-    if (tile_blocks < 64 || tile_blocks > kMaxTileBlocks)
-        return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d]", tile_blocks, kMaxTileBlocks);
+    if (tile_blocks != 0 && (tile_blocks < 64 || tile_blocks > kMaxTileBlocks))
+        return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d] (or 0)", tile_blocks, kMaxTileBlocks);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tiling after upload");
-    try {
-        nsa_status st = build_tiles(m, m->plan[scatter], tile_blocks, kPlanThreads[scatter], scatter == NSA_COLOUR);
-        if (st) return st;
-        plan_layout(m);
-    } catch (const std::bad_alloc &) {
-        return fail(NSA_ENOMEM, "nsa_mesh_set_tiling: host allocation failed");
+    std::lock_guard<std::mutex> g(m->plan_mu);
+    if (m->want_blocks[scatter] != tile_blocks || !m->planned) {
+        m->want_blocks[scatter] = tile_blocks;
+        m->planned = false;
     }
     return ok();
 }
@@ -557,6 +570,10 @@ nsa_status nsa_mesh_destroy(nsa_mesh *m) {
 
 nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
     if (!m || !info) return fail(NSA_EINVAL, "nsa_mesh_get_info: null argument");
+    if (!m->host_released) {
+        nsa_status st = ensure_plans(m);
+        if (st) return st;
+    }
     info->npoin = m->npoin;
     info->nelem = m->nelem;
     info->nnzb = m->nnzb;
@@ -598,9 +615,11 @@ nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_
                               uint8_t *records) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_tiles: null mesh");
     if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    nsa_status st = ensure_plans(m);
+    if (st) return st;
     const nsa::TilePlan &P = m->plan[scatter];
     if (!P.ok) return fail(NSA_EUNSUPPORTED, "no tile plan for this mesh");
-    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     if (tile_row) std::copy(P.row.begin(), P.row.end(), tile_row);
     if (tile_eptr) std::copy(P.eptr.begin(), P.eptr.end(), tile_eptr);
     if (elems) std::copy(P.elems.begin(), P.elems.end(), elems);
@@ -614,6 +633,10 @@ nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_
 nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream) {
     if (!m || !ws) return fail(NSA_EINVAL, "nsa_mesh_upload: null argument");
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    {
+        nsa_status st0 = ensure_plans(m);
+        if (st0) return st0;
+    }
     if (ws_bytes < m->ws_bytes)
         return fail(NSA_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, m->ws_bytes);
     if (((uintptr_t)ws) % 256) return fail(NSA_EINVAL, "workspace not 256-byte aligned");
@@ -787,4 +810,210 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
     return ok();
 }
 
+// ---- batched form ----------------------------------------------------------------------------
+
 }  // extern "C"
+
+struct nsa_batch {
+    int32_t scatter = 0;
+    std::vector<const nsa_mesh *> meshes;
+    std::vector<int2> work;          // (mesh, local tile), each mesh's tiles contiguous
+    int64_t lds = 0;
+    int32_t threads = 256;
+    int32_t ncu = 256;
+    int64_t elements = 0;
+    int device = -1;
+    nsa::Region r_work, r_desc;
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    nsa::TileArgs *staging = nullptr;  // pinned host copy of the descriptors
+    hipEvent_t copied = nullptr;       // completion of the last descriptor upload
+    bool inputs_set = false;
+    ~nsa_batch() {
+        // errors cannot be reported from a destructor; the handles are released either way
+        if (copied) {
+            (void)hipEventSynchronize(copied);
+            (void)hipEventDestroy(copied);
+        }
+        if (staging) (void)hipHostFree(staging);
+    }
+};
+
+extern "C" {
+
+nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out) {
+    if (!out || nmesh <= 0 || !meshes) return fail(NSA_EINVAL, "nsa_batch_create: bad arguments");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    *out = nullptr;
+    int dev = -1;
+    for (int32_t i = 0; i < nmesh; i++) {
+        const nsa_mesh *m = meshes[i];
+        if (!m) return fail(NSA_EINVAL, "mesh %d is null", i);
+        if (!m->ws) return fail(NSA_ESTATE, "mesh %d is not uploaded", i);
+        if (!m->plan[scatter].ok && m->nelem > 0)
+            return fail(NSA_EUNSUPPORTED, "mesh %d cannot use the tiled kernel", i);
+        if (i == 0) dev = m->device;
+        if (m->device != dev) return fail(NSA_EINVAL, "meshes are on different devices");
+    }
+    nsa_batch *b = nullptr;
+    try {
+        b = new nsa_batch;
+        b->scatter = scatter;
+        b->device = dev;
+        b->meshes.assign(meshes, meshes + nmesh);
+        b->threads = meshes[0]->plan[scatter].threads;
+        for (int32_t i = 0; i < nmesh; i++) {
+            const nsa::TilePlan &P = meshes[i]->plan[scatter];
+            if (P.ok && P.threads != b->threads) {
+                delete b;
+                return fail(NSA_EUNSUPPORTED, "meshes planned for different workgroup sizes");
+            }
+            b->lds = std::max<int64_t>(b->lds, P.lds);
+            b->elements += meshes[i]->nelem;
+            for (int64_t t = 0; t < P.ntiles(); t++) b->work.push_back(make_int2(i, (int)t));
+        }
+        if (b->work.size() > (size_t)INT32_MAX) {
+            delete b;
+            return fail(NSA_EUNSUPPORTED, "too many tiles in one batch");
+        }
+        size_t off = 0;
+        b->r_work.off = 0;
+        b->r_work.bytes = std::max<size_t>(1, b->work.size()) * sizeof(int2);
+        off = align_up(b->r_work.bytes);
+        b->r_desc.off = off;
+        b->r_desc.bytes = (size_t)nmesh * sizeof(nsa::TileArgs);
+        b->ws_bytes = align_up(off + b->r_desc.bytes);
+        nsa_status st = hip_check(hipHostMalloc((void **)&b->staging, b->r_desc.bytes, hipHostMallocDefault),
+                                  "hipHostMalloc");
+        if (!st) st = hip_check(hipEventCreateWithFlags(&b->copied, hipEventDisableTiming), "hipEventCreate");
+        if (!st) st = hip_check(hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev),
+                                "hipDeviceGetAttribute");
+        if (st) {
+            delete b;
+            return st;
+        }
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return fail(NSA_ENOMEM, "nsa_batch_create: host allocation failed");
+    }
+    *out = b;
+    return ok();
+}
+
+nsa_status nsa_batch_destroy(nsa_batch *b) {
+    delete b;
+    return ok();
+}
+
+nsa_status nsa_batch_get_info(const nsa_batch *b, size_t *ws_bytes, int64_t *ntiles, int64_t *nelem,
+                              int32_t *lds_bytes) {
+    if (!b) return fail(NSA_EINVAL, "nsa_batch_get_info: null batch");
+    if (ws_bytes) *ws_bytes = b->ws_bytes;
+    if (ntiles) *ntiles = (int64_t)b->work.size();
+    if (nelem) *nelem = b->elements;
+    if (lds_bytes) *lds_bytes = (int32_t)b->lds;
+    return ok();
+}
+
+nsa_status nsa_batch_upload(nsa_batch *b, void *ws, size_t ws_bytes, void *stream) {
+    if (!b || !ws) return fail(NSA_EINVAL, "nsa_batch_upload: null argument");
+    if (ws_bytes < b->ws_bytes) return fail(NSA_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, b->ws_bytes);
+    if (((uintptr_t)ws) % 256) return fail(NSA_EINVAL, "workspace not 256-byte aligned");
+    int dev = -1;
+    nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != b->device) return fail(NSA_EINVAL, "batch meshes live on device %d, current is %d", b->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    b->ws = (char *)ws;
+    if (!b->work.empty()) {
+        st = hip_check(hipMemcpyAsync(b->ws + b->r_work.off, b->work.data(), b->work.size() * sizeof(int2),
+                                      hipMemcpyHostToDevice, s), "batch upload");
+        if (st) return st;
+    }
+    st = hip_check(hipStreamSynchronize(s), "batch upload sync");
+    if (!st) st = hip_check(nsa::prepare_batch(b->threads, (size_t)b->lds), "batch LDS limit");
+    return st ? st : ok();
+}
+
+nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const double *rho, const double *mu,
+                                const double *dt, double *const *values, double *const *rhs, int32_t accumulate,
+                                void *stream) {
+    if (!b || !vel || !rho || !mu || !dt || !values || !rhs) return fail(NSA_EINVAL, "nsa_batch_set_inputs: null argument");
+    if (!b->ws) return fail(NSA_ESTATE, "nsa_batch_set_inputs before nsa_batch_upload");
+    if (accumulate != 0 && accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
+    // the staging buffer may still feed the previous upload
+    nsa_status st = hip_check(hipEventSynchronize(b->copied), "batch staging wait");
+    if (st) return st;
+    for (size_t i = 0; i < b->meshes.size(); i++) {
+        const nsa_mesh *m = b->meshes[i];
+        const nsa::TilePlan &P = m->plan[b->scatter];
+        if (!(rho[i] > 0.0) || !std::isfinite(rho[i]) || !(mu[i] >= 0.0) || !std::isfinite(mu[i]) ||
+            !(dt[i] > 0.0) || !std::isfinite(dt[i]))
+            return fail(NSA_EINVAL, "mesh %zu: need rho > 0, mu >= 0, dt > 0 (finite)", i);
+        if ((m->nelem > 0 && !vel[i]) || (m->nnzb > 0 && !values[i]) || (m->npoin > 0 && !rhs[i]))
+            return fail(NSA_EINVAL, "mesh %zu: null device array", i);
+        if (((uintptr_t)values[i] | (uintptr_t)rhs[i]) % 16) return fail(NSA_EINVAL, "mesh %zu: misaligned output", i);
+        nsa::TileArgs t;
+        if (P.ok) {
+            t.ntiles = P.ntiles();
+            t.lds_bytes = P.lds;
+            t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
+            t.tile_eptr = (const int64_t *)(m->ws + P.r_eptr.off);
+            t.rec = (const uint2 *)(m->ws + P.r_recs.off);
+            t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
+            t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
+            t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
+            t.coord = (const double4 *)(m->ws + m->r_coord4.off);
+        }
+        t.vel = vel[i];
+        t.rho = rho[i];
+        t.mu = mu[i];
+        t.dt = dt[i];
+        t.accumulate = accumulate;
+        t.threads = b->threads;
+        t.values = values[i];
+        t.rhs = rhs[i];
+        b->staging[i] = t;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = hip_check(hipMemcpyAsync(b->ws + b->r_desc.off, b->staging, b->r_desc.bytes, hipMemcpyHostToDevice, s),
+                   "batch descriptor upload");
+    if (!st) st = hip_check(hipEventRecord(b->copied, s), "batch event");
+    if (st) return st;
+    b->inputs_set = true;
+    return ok();
+}
+
+nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream) {
+    if (!b) return fail(NSA_EINVAL, "nsa_assemble_batched: null batch");
+    if (!b->ws || !b->inputs_set) return fail(NSA_ESTATE, "nsa_assemble_batched before upload / set_inputs");
+    nsa_options o{};
+    if (opt) o = *opt;
+    if (o.precision != NSA_FP64 && o.precision != NSA_MIXED) return fail(NSA_EINVAL, "unknown precision %d", o.precision);
+    if (o.scatter != b->scatter) return fail(NSA_EINVAL, "batch was built for scatter mode %d", b->scatter);
+    if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
+    for (int r : o.reserved)
+        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    const int64_t total = (int64_t)b->work.size();
+    if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
+    int64_t g = grid_wgs ? grid_wgs : (int64_t)b->ncu * (b->threads == 64 ? 4 : 2);
+    g = std::min<int64_t>(g, (total + 7) / 8 * 8);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    int dev = -1;
+    nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != b->device) return fail(NSA_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+    // the throughput plan accepts a workgroup-size override for tuning; the deterministic plan needs
+    // one wavefront per tile
+    const int threads = (b->scatter == NSA_ATOMIC && (o.block_threads == 128 || o.block_threads == 256))
+                            ? o.block_threads : b->threads;
+    st = hip_check(nsa::launch_tiled_batch(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64,
+                                           (const nsa::TileArgs *)(b->ws + b->r_desc.off),
+                                           (const int2 *)(b->ws + b->r_work.off), total, threads, b->lds,
+                                           (int)g, (hipStream_t)stream),
+                   "assemble (batched)");
+    return st ? st : ok();
+}
+
+}  // extern "C"
+

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,10 @@ __host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows
 enum class TileKern { F64, Mixed };
 size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);
+// Batched persistent form: desc[mesh] in device memory, work[t] = (mesh, local tile).
+hipError_t prepare_batch(int threads, size_t lds);
+hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
+                              int64_t lds, int grid_wgs, hipStream_t s);
 
 // A row-tile plan for one scatter mode (host copy, then device regions after upload).
 struct TilePlan {
@@ -120,8 +125,12 @@ struct nsa_mesh {
     std::vector<int32_t> emap;          // [nelem][16]
     std::vector<int32_t> colour_ptr;    // [ncolours+1]
     std::vector<int32_t> colour_elems;  // [nelem]
-    // row-tile plans: [NSA_ATOMIC] throughput plan, [NSA_COLOUR] deterministic plan
+    // row-tile plans: [NSA_ATOMIC] throughput plan, [NSA_COLOUR] deterministic plan; built on first
+    // need (info, tiles, upload) from the requested sizes (0 = no plan for that mode)
     nsa::TilePlan plan[2];
+    int32_t want_blocks[2] = {0, 0};
+    bool planned = false;
+    std::mutex plan_mu;
     // device layout (offsets into the caller's workspace)
     nsa::Region r_ln, r_coord, r_emap, r_ln_c, r_emap_c, r_coord4, r_bptr;
     size_t ws_bytes = 0;

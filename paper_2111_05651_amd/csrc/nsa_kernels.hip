@@ -21,6 +21,9 @@
 // contribution is converted to FP64 before it is added into the global arrays.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "nsa_internal.h"
 
 namespace nsa {
@@ -489,14 +492,10 @@ __device__ __forceinline__ void tile_element(const TileArgs &A, const Rec &rc, i
     }
 }
 
+// One tile from prologue to write-out. Ends with a barrier so that the caller may start the next
+// tile's prologue on the same LDS.
 template <typename R, int NT>
-__global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
-    extern __shared__ double smem[];
-    // XCD-aware order: workgroup w runs on XCD w % 8, so give each XCD a contiguous run of tiles
-    // (neighbouring tiles share nodal data in that XCD's L2).
-    const int64_t per = (A.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= A.ntiles) return;
+__device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double *smem) {
     const int tid = threadIdx.x;
     const int r0 = A.tile_row[tile], r1 = A.tile_row[tile + 1], nrows = r1 - r0;
     const int64_t b0 = A.bptr[r0];
@@ -561,12 +560,54 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
         if (A.accumulate) v += rout[i];
         rout[i] = v;
     }
+    __syncthreads();
+}
+
+template <typename R, int NT>
+__global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
+    extern __shared__ double smem[];
+    // XCD-aware order: workgroup w runs on XCD w % 8, so give each XCD a contiguous run of tiles
+    // (neighbouring tiles share nodal data in that XCD's L2).
+    const int64_t per = (A.ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= A.ntiles) return;
+    run_tile<R, NT>(A, tile, smem);
+}
+
+// Persistent batched form: a grid of resident workgroups walks the tiles of many meshes. work[t] =
+// (mesh, tile of that mesh) with each mesh's tiles contiguous; desc[mesh] holds that mesh's
+// arrays, outputs and parameters. Workgroup w runs on XCD w % 8; XCD x owns the contiguous slice
+// [x*per, (x+1)*per) of the work table and its workgroups take every (G/8)-th tile of it.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *desc, const int2 *work, int64_t total) {
+    extern __shared__ double smem[];
+    const int64_t nslot = gridDim.x >> 3;
+    const int64_t per = (total + 7) / 8;
+    const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
+    const int64_t hi = lo + per < total ? lo + per : total;
+    for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nslot) {
+        const int2 w = work[t];
+        const TileArgs A = desc[w.x];
+        run_tile<R, NT>(A, w.y, smem);
+    }
 }
 
 }  // namespace
 
 size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
     return (size_t)lds_rowoff_off(cap_blocks, cap_rows, cap_nodes) * 8 + (size_t)cap_rows * 4;
+}
+
+// Raise a kernel's dynamic-LDS limit once (not at every launch, so launches can be captured).
+static hipError_t ensure_lds(const void *kern, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> g(mu);
+    size_t &have = done[kern];
+    if (have >= bytes) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) have = bytes;
+    return e;
 }
 
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
@@ -576,8 +617,7 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     const int nt = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
     const dim3 grid((unsigned)(8 * per)), block(nt);
     auto go = [&](auto kern) -> hipError_t {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = ensure_lds(reinterpret_cast<const void *>(kern), lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, grid, block, lds, s, a);
         return hipGetLastError();
@@ -585,8 +625,39 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     const bool mixed = k == TileKern::Mixed;
     if (nt == 64) return mixed ? go(k_tiled<float, 64>) : go(k_tiled<double, 64>);
     if (nt == 128) return mixed ? go(k_tiled<float, 128>) : go(k_tiled<double, 128>);
-    if (nt == 256) return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
-    return hipErrorInvalidValue;
+    return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
+}
+
+hipError_t prepare_batch(int threads, size_t lds) {
+    hipError_t e = hipSuccess;
+    for (const void *k : {reinterpret_cast<const void *>(k_tiled_batch<double, 64>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 64>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 128>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 128>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 256>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 256>)})
+        if (e == hipSuccess) e = ensure_lds(k, lds);
+    (void)threads;
+    return e;
+}
+
+hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
+                              int64_t lds, int grid_wgs, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    const int nt = (threads == 64 || threads == 128) ? threads : 256;
+    const dim3 grid((unsigned)grid_wgs), block(nt);
+    const bool mixed = k == TileKern::Mixed;
+#define NSA_LAUNCH_BATCH(T, N) \
+    hipLaunchKernelGGL((k_tiled_batch<T, N>), grid, block, (size_t)lds, s, desc, work, total)
+    if (nt == 64) {
+        if (mixed) NSA_LAUNCH_BATCH(float, 64); else NSA_LAUNCH_BATCH(double, 64);
+    } else if (nt == 128) {
+        if (mixed) NSA_LAUNCH_BATCH(float, 128); else NSA_LAUNCH_BATCH(double, 128);
+    } else {
+        if (mixed) NSA_LAUNCH_BATCH(float, 256); else NSA_LAUNCH_BATCH(double, 256);
+    }
+#undef NSA_LAUNCH_BATCH
+    return hipGetLastError();
 }
 
 }  // namespace nsa

@@ -22,7 +22,9 @@ KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT = 0, 1, 2
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
-           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble"]
+           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
+           "nsa_batch_create", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
+           "nsa_assemble_batched"]
 
 
 class NsaError(RuntimeError):
@@ -73,6 +75,12 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
     lib.nsa_mesh_release_host.argtypes = [P]
     lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
+    lib.nsa_batch_create.argtypes = [i32, P, i32, C.POINTER(P)]
+    lib.nsa_batch_destroy.argtypes = [P]
+    lib.nsa_batch_get_info.argtypes = [P, P, P, P, P]
+    lib.nsa_batch_upload.argtypes = [P, P, sz, P]
+    lib.nsa_batch_set_inputs.argtypes = [P, P, P, P, P, P, P, i32, P]
+    lib.nsa_assemble_batched.argtypes = [P, C.POINTER(Options), i32, P]
     for name in EXPORTS:
         if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
             getattr(lib, name).restype = i32
@@ -236,3 +244,52 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
     _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
                                _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
     return values, rhs
+
+
+class Batch:
+    """Many uploaded meshes assembled by one persistent launch (nsa_batch_*). Keeps references to
+    the meshes, its device workspace and the last inputs so that nothing it points at is freed."""
+
+    def __init__(self, meshes, scatter=ATOMIC, device="cuda", stream=None):
+        import torch
+        lib = load()
+        self.meshes = list(meshes)
+        self.scatter = int(scatter)
+        arr = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
+        h = C.c_void_p()
+        _check(lib.nsa_batch_create(len(self.meshes), arr, self.scatter, C.byref(h)), "nsa_batch_create")
+        self._h = h
+        ws, nt, ne, lds = C.c_size_t(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib.nsa_batch_get_info(h, C.byref(ws), C.byref(nt), C.byref(ne), C.byref(lds)), "nsa_batch_get_info")
+        self.ntiles, self.nelem, self.lds_bytes = nt.value, ne.value, lds.value
+        self.ws = torch.empty(int(ws.value), dtype=torch.uint8, device=device)
+        _check(lib.nsa_batch_upload(h, self.ws.data_ptr(), int(ws.value), _stream_handle(stream)), "nsa_batch_upload")
+        self._keep = None
+
+    def alloc_outputs(self, device="cuda"):
+        return [m.alloc_outputs(device) for m in self.meshes]
+
+    def set_inputs(self, vels, rho, mu, dt, outputs, accumulate=False, stream=None):
+        """vels: device tensors [npoin][3]; rho, mu, dt: sequences; outputs: [(values, rhs), ...]."""
+        n = len(self.meshes)
+        P = C.c_void_p
+        v = (P * n)(*[x.data_ptr() for x in vels])
+        va = (P * n)(*[o[0].data_ptr() for o in outputs])
+        ra = (P * n)(*[o[1].data_ptr() for o in outputs])
+        dr = (C.c_double * n)(*[float(x) for x in rho])
+        dm = (C.c_double * n)(*[float(x) for x in mu])
+        dd = (C.c_double * n)(*[float(x) for x in dt])
+        _check(load().nsa_batch_set_inputs(self._h, v, dr, dm, dd, va, ra, int(bool(accumulate)),
+                                           _stream_handle(stream)), "nsa_batch_set_inputs")
+        self._keep = (list(vels), list(outputs))
+
+    def assemble(self, precision=MIXED, grid_wgs=0, block_threads=0, stream=None):
+        o = make_options(precision, self.scatter, block_threads=block_threads)
+        _check(load().nsa_assemble_batched(self._h, C.byref(o), int(grid_wgs), _stream_handle(stream)),
+               "nsa_assemble_batched")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.nsa_batch_destroy(h)
+            self._h = None

@@ -201,8 +201,14 @@ def test_tile_plan_defaults(lib):
 def test_tiling_arguments(lib):
     m = inputs.make_mesh(2, seed=34)
     mesh = nsa.Mesh.from_inputs(m)
-    for bad in (0, 63, 1025):
+    for bad in (-1, 63, 1025):
         with pytest.raises(nsa.NsaError):
             mesh.set_tiling(bad)
     with pytest.raises(nsa.NsaError):
         mesh.set_tiling(256, scatter=7)
+    # 0 drops the plan of that mode
+    mesh.set_tiling(0, scatter=nsa.COLOUR)
+    assert mesh.info.ntiles[nsa.COLOUR] == 0 and mesh.info.ntiles[nsa.ATOMIC] > 0
+    with pytest.raises(nsa.NsaError) as ei:
+        mesh.tiles(nsa.COLOUR)
+    assert ei.value.status == nsa.NSA_EUNSUPPORTED
