@@ -10,6 +10,7 @@ geometry and accumulation, FP32 element integration); the plain FP64 kernel is t
 the same GPU. Prints one JSON line.
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -168,12 +169,150 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args):
+    """Served load: 200 resident jittered cubes (tets log-uniform in [1e3, 5e6]), open-loop Poisson
+    arrivals, one request = one assembly of a uniformly chosen mesh with a velocity drawn on the
+    device from the request's seed and its own rho, mu, dt. The arrival rate is set to a fraction of
+    the batched form's throughput on the 64-mesh batch (measured first, same run). The server runs
+    continuous batching (mixed precision); beside it, plain FP64 launches served one at a time on
+    the same resident meshes and the same arrival stream."""
+    import math
+    import threading
+    import torch
+    from paper_2111_05651_amd import inputs, nsa
+    from paper_2111_05651_amd.serve import DONE, GpuExecutor, Server
+    scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
+    prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
+    # reference rate: the 64-mesh batch, one persistent launch (default plan)
+    t0 = time.perf_counter()
+    c4 = inputs.config_batch()
+    hs = [nsa.Mesh.from_inputs(m, tile_blocks=512 if scat == nsa.ATOMIC else 0,
+                               tile_blocks_colour=0 if scat == nsa.ATOMIC else 256).upload() for m in c4]
+    b = nsa.Batch(hs, scat)
+    vels = [torch.from_numpy(m.velocity).cuda() for m in c4]
+    outs = b.alloc_outputs()
+    b.set_inputs(vels, [m.rho for m in c4], [m.mu for m in c4], [m.dt for m in c4], outs)
+    ms4, _, _ = time_steps(lambda: b.assemble(prec), 10, 3, torch.cuda.current_stream())
+    rate4 = sum(m.nelem for m in c4) / (ms4 / 1e3)
+    log(f"64-mesh batch: {ms4:.3f} ms, {rate4:.4g} elements/s ({time.perf_counter() - t0:.1f} s)")
+    del c4, hs, b, vels, outs
+    torch.cuda.empty_cache()
+    # resident meshes
+    t0 = time.perf_counter()
+    meshes = inputs.config_served(nmesh=args.serve_meshes)
+    log(f"{len(meshes)} served meshes generated, {sum(m.nelem for m in meshes)} tets "
+        f"({time.perf_counter() - t0:.1f} s)")
+    ex = GpuExecutor(meshes, scatter=scat, precision=prec, slots=args.serve_slots, trace=True, log=log)
+    sizes = [(h.nelem, h.npoin, h.nnzb) for h in ex.meshes]
+    del meshes
+    log(f"resident: {ex.resident_bytes / 1e9:.2f} GB ({time.perf_counter() - t0:.1f} s)")
+    plain = GpuExecutor(None, scatter=scat, precision=nsa.FP64, mode="plain", trace=True, resident=ex.meshes)
+    mean_elems = sum(x[0] for x in sizes) / len(sizes)
+
+    def run(executor, frac, seed):
+        lam = frac * rate4 / mean_elems
+        nreq = max(1, int(math.ceil(lam * args.serve_seconds)))
+        stream = inputs.served_requests(nreq, len(sizes), rate=lam, seed=seed)
+        srv = Server(executor, budget_bytes=int(args.serve_budget_gb * 2 ** 30), timeout=60.0,
+                     max_launch_elems=args.serve_launch_elems)
+        executor.intervals.clear()
+        reqs = []
+        gc.collect()
+        pauses, t_gc = [], [0.0]
+
+        def on_gc(phase, info):
+            if phase == "start":
+                t_gc[0] = time.perf_counter()
+            else:
+                pauses.append(time.perf_counter() - t_gc[0])
+        gc.callbacks.append(on_gc)
+        if args.serve_gc == "paused":
+            # the load generator's own policy: long-lived objects frozen, the cyclic collector off
+            # during the arrival window (reference counting still frees everything)
+            gc.freeze()
+            gc.disable()
+        mem0 = torch.cuda.memory_stats()
+        with srv:
+            start = time.perf_counter() + 0.05
+
+            def client():
+                for q in stream:
+                    wait = start + q["t"] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    reqs.append(srv.submit(q["mesh"], q["rho"], q["mu"], q["dt"], vel_seed=q["vel_seed"],
+                                           arrival=start + q["t"]))
+            th = threading.Thread(target=client)
+            th.start()
+            th.join()
+            for r in reqs:
+                r.wait(120.0)
+        gc.enable()
+        gc.unfreeze()
+        gc.callbacks.remove(on_gc)
+        mem1 = torch.cuda.memory_stats()
+        st = srv.stats(t_start=start)
+        ov = executor.device_overlap()
+        done = [r for r in reqs if r.status == DONE]
+        wait = [r.t_launch - r.t_arrival for r in done]
+        service = [r.t_done - r.t_launch for r in done]
+
+        def pct(x, q):
+            return float(statistics.quantiles(x, n=100)[q - 1]) * 1e3 if len(x) > 1 else float("nan")
+        nbytes = sum(algorithmic_bytes(*sizes[r.mesh_id]) for r in done)
+        busy = ov.get("busy_ms", 0.0)
+        out = {"load": frac, "rate_per_s": lam, "requests": nreq, "done": len(done),
+               "p50_ms": st.get("p50", float("nan")) * 1e3, "p99_ms": st.get("p99", float("nan")) * 1e3,
+               "mean_ms": st.get("mean", float("nan")) * 1e3, "elements_per_s": st.get("elements_per_s"),
+               "offered_elements_per_s": lam * mean_elems, "launches": st["launches"],
+               "mean_launch_requests": st["mean_launch_requests"], "max_inflight": st["max_inflight"],
+               "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9, "rejected": st["rejected"],
+               "timeouts": st["timeout"], "device_busy_ms": busy,
+               "device_overlapping_launches": ov.get("overlapping", 0),
+               "hbm_GBs_while_busy": nbytes / (busy / 1e3) / 1e9 if busy > 0 else None,
+               "wait_ms_p50_p99": [pct(wait, 50), pct(wait, 99)],
+               "service_ms_p50_p99": [pct(service, 50), pct(service, 99)],
+               "gc_pauses": len(pauses), "gc_max_pause_ms": max(pauses, default=0.0) * 1e3,
+               "device_mallocs": mem1.get("num_device_alloc", 0) - mem0.get("num_device_alloc", 0),
+               "device_frees": mem1.get("num_device_free", 0) - mem0.get("num_device_free", 0)}
+        log(f"{'batched' if executor.mode == 'batched' else 'plain FP64'} at {frac:.0%}: "
+            f"{json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()})}")
+        return out
+
+    loads = [float(x) for x in args.serve_loads.split(",")]
+    served = [run(ex, f, 60 + k) for k, f in enumerate(loads)]
+    base = [run(plain, f, 60 + k) for k, f in enumerate(loads)]
+    head = served[-1]
+    hbm = head["hbm_GBs_while_busy"]
+    line = {
+        "metric": "elements assembled/s under served load (p50/p99 latency)", "value": head["elements_per_s"],
+        "unit": "elements/s", "n_gpus": 1, "steps": head["requests"], "warmup": 0, "ms_per_step": head["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == nsa.MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"served: {len(sizes)} resident jittered cubes, tets log-uniform in [1e3, 5e6]; "
+                               f"Poisson arrivals at {head['load']:.0%} of the 64-mesh batched throughput",
+                   "nmesh": len(sizes), "resident_elements": int(sum(x[0] for x in sizes)),
+                   "budget_GB": args.serve_budget_gb, "slots": args.serve_slots, "scatter": args.scatter,
+                   "precision": args.precision, "reference_batched_elements_per_s": rate4,
+                   "seconds_of_arrivals": args.serve_seconds, "launch_elems_cap": args.serve_launch_elems,
+                   "python_gc": args.serve_gc},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+        "roofline": {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": hbm / PEAK_HBM_GBS if hbm else None, "traffic": None, "kernel": "k_tiled_batch",
+                     "note": "algorithmic bytes of the completed requests over the device-busy time"},
+        "cpu_baseline": None,
+        "loads": served,
+        "plain_fp64_one_at_a_time": base,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8", "batch64"])
+    ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8", "batch64", "serve"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
     ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto"])
@@ -182,6 +321,14 @@ def main():
     ap.add_argument("--no-baseline-fp64", action="store_true", help="skip timing the FP64 kernel beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="elements for the CPU baseline (0 = the whole mesh)")
+    ap.add_argument("--serve-meshes", type=int, default=200)
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="seconds of arrivals per load level")
+    ap.add_argument("--serve-loads", default="0.5,0.8", help="arrival rates as fractions of the batched rate")
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-launch-elems", type=int, default=4_000_000, help="element cap of one served launch")
+    ap.add_argument("--serve-gc", default="paused", choices=["paused", "default"],
+                    help="Python's cyclic collector during the arrival window")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="instead: time a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -206,6 +353,8 @@ def main():
         return
     if args.workload == "batch64":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
     prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
     scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
     kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO}[args.kernel]

@@ -146,6 +146,10 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
  * (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be called before nsa_mesh_upload
  * (NSA_ESTATE after). */
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks);
+/* Whether nsa_mesh_upload also stores the direct kernel's arrays (SoA connectivity, element-to-block
+ * map and their colour-ordered copies, ~160 bytes per element; default 1). With 0 the mesh can only
+ * be assembled by the tiled kernel (NSA_KERNEL_DIRECT returns NSA_EUNSUPPORTED). Before upload. */
+nsa_status nsa_mesh_keep_direct(nsa_mesh *m, int32_t keep);
 nsa_status nsa_mesh_destroy(nsa_mesh *m);
 nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info);
 /* Copy the block pattern out (host arrays of the sizes given by nsa_mesh_get_info: bptr
@@ -197,13 +201,25 @@ typedef struct nsa_batch nsa_batch; /* opaque */
  * have a tile plan for `scatter` (NSA_EUNSUPPORTED otherwise). The meshes must outlive the batch. */
 nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out);
 nsa_status nsa_batch_destroy(nsa_batch *b);
-/* Device workspace the batch needs, total tiles and elements, LDS per workgroup (any may be NULL). */
+/* A reusable batch for continuous batching: room for up to max_meshes members with max_tiles tiles of
+ * the plan for `scatter` in total; its members are chosen, and changed between launches, with
+ * nsa_batch_reset. Upload it once (the workspace is sized for the capacity). */
+nsa_status nsa_batch_reserve(int32_t max_meshes, int64_t max_tiles, int32_t scatter, nsa_batch **out);
+/* Replace the members of a batch (same conditions as nsa_batch_create; a mesh may appear more than
+ * once, each entry with its own inputs). NSA_ENOMEM if they exceed the capacity. Host only: the new
+ * work table reaches the device with the next nsa_batch_set_inputs, which must come before the next
+ * launch. Waits until the previous upload has finished reading the host staging buffer. The device
+ * copy is rewritten in stream order: a launch of the same batch still running on another stream
+ * would race with it. */
+nsa_status nsa_batch_reset(nsa_batch *b, int32_t nmesh, const nsa_mesh *const *meshes);
+/* Device workspace the batch needs (for its capacity), the current members' total tiles and
+ * elements, LDS per workgroup (any may be NULL). */
 nsa_status nsa_batch_get_info(const nsa_batch *b, size_t *ws_bytes, int64_t *ntiles, int64_t *nelem,
                               int32_t *lds_bytes);
-/* Copy the work table into ws (device, >= ws_bytes, 256-byte aligned, caller-owned, kept alive while
- * the batch is used). Synchronous. */
+/* Attach the workspace ws (device, >= ws_bytes, 256-byte aligned, caller-owned, kept alive while the
+ * batch is used) and copy the work table into it, ordered on stream. */
 nsa_status nsa_batch_upload(nsa_batch *b, void *ws, size_t ws_bytes, void *stream);
-/* Per-mesh inputs and outputs (arrays of nmesh entries, in the order of nsa_batch_create): device
+/* Per-mesh inputs and outputs (arrays of nmesh entries, in member order): device
  * velocity [npoin][3], rho > 0, mu >= 0, dt > 0, device values [nnzb][4][4] and rhs [npoin][4]
  * (16-byte aligned); accumulate as in nsa_options. Stream-ordered copy of the per-mesh descriptors
  * into the batch workspace (waits for the previous call's copy to finish reading its host staging).

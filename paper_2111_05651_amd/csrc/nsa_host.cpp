@@ -378,11 +378,12 @@ void plan_layout(nsa_mesh *m) {
         off = align_up(off + bytes);
     };
     const size_t ne = (size_t)m->nelem, np = (size_t)m->npoin;
-    take(m->r_ln, 4 * ne * sizeof(int32_t));
-    take(m->r_coord, 3 * np * sizeof(double));
-    take(m->r_emap, 16 * ne * sizeof(int32_t));
-    take(m->r_ln_c, 4 * ne * sizeof(int32_t));
-    take(m->r_emap_c, 16 * ne * sizeof(int32_t));
+    const bool d = m->keep_direct;
+    take(m->r_ln, d ? 4 * ne * sizeof(int32_t) : 0);
+    take(m->r_coord, d ? 3 * np * sizeof(double) : 0);
+    take(m->r_emap, d ? 16 * ne * sizeof(int32_t) : 0);
+    take(m->r_ln_c, d ? 4 * ne * sizeof(int32_t) : 0);
+    take(m->r_emap_c, d ? 16 * ne * sizeof(int32_t) : 0);
     const bool t = m->plan[0].ok || m->plan[1].ok;
     take(m->r_coord4, t ? 4 * np * sizeof(double) : 0);
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
@@ -563,6 +564,17 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
     return ok();
 }
 
+nsa_status nsa_mesh_keep_direct(nsa_mesh *m, int32_t keep) {
+    if (!m || (keep != 0 && keep != 1)) return fail(NSA_EINVAL, "nsa_mesh_keep_direct: bad arguments");
+    if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_keep_direct after upload");
+    std::lock_guard<std::mutex> g(m->plan_mu);
+    if (m->keep_direct != (keep == 1)) {
+        m->keep_direct = keep == 1;
+        if (m->planned) plan_layout(m);  // tile plans stay; only the workspace layout changes
+    }
+    return ok();
+}
+
 nsa_status nsa_mesh_destroy(nsa_mesh *m) {
     delete m;
     return ok();
@@ -643,9 +655,10 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
     hipStream_t s = (hipStream_t)stream;
     const int64_t ne = m->nelem, np = m->npoin;
     try {
-        std::vector<int32_t> ln(4 * ne), em(16 * ne), lnc(4 * ne), emc(16 * ne);
-        std::vector<double> co(3 * np);
-        parallel_for(ne, [&](int64_t b, int64_t e) {
+        const bool d = m->keep_direct;
+        std::vector<int32_t> ln(d ? 4 * ne : 0), em(d ? 16 * ne : 0), lnc(d ? 4 * ne : 0), emc(d ? 16 * ne : 0);
+        std::vector<double> co(d ? 3 * np : 0);
+        if (d) parallel_for(ne, [&](int64_t b, int64_t e) {
             for (int64_t i = b; i < e; i++) {
                 for (int a = 0; a < 4; a++) ln[a * ne + i] = m->lnods[4 * i + a];
                 for (int k = 0; k < 16; k++) em[k * ne + i] = m->emap[16 * i + k];
@@ -654,8 +667,9 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
                 for (int k = 0; k < 16; k++) emc[k * ne + i] = m->emap[16 * src + k];
             }
         });
-        for (int64_t i = 0; i < np; i++)
-            for (int d = 0; d < 3; d++) co[d * np + i] = m->coord[3 * i + d];
+        if (d)
+            for (int64_t i = 0; i < np; i++)
+                for (int c = 0; c < 3; c++) co[c * np + i] = m->coord[3 * i + c];
         std::vector<double> co4;
         if (m->plan[0].ok || m->plan[1].ok) {
             co4.assign(4 * (size_t)np, 0.0);
@@ -769,6 +783,8 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         st = hip_check(nsa::launch_tiled(mixed ? nsa::TileKern::Mixed : nsa::TileKern::F64, t, s), "assemble (tiled)");
         return st ? st : ok();
     }
+    if (!m->keep_direct)
+        return fail(NSA_EUNSUPPORTED, "the direct kernel's data of this mesh was not uploaded (nsa_mesh_keep_direct)");
     if (!o.accumulate) {
         st = hip_check(nsa::launch_fill_zero(values, 16 * m->nnzb, s), "zero values");
         if (st) return st;
@@ -816,8 +832,11 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
 
 struct nsa_batch {
     int32_t scatter = 0;
+    // capacity (fixed at creation) and current members
+    int32_t cap_meshes = 0;
+    int64_t cap_tiles = 0;
     std::vector<const nsa_mesh *> meshes;
-    std::vector<int2> work;          // (mesh, local tile), each mesh's tiles contiguous
+    int64_t ntiles = 0;
     int64_t lds = 0;
     int32_t threads = 256;
     int32_t ncu = 256;
@@ -826,9 +845,14 @@ struct nsa_batch {
     nsa::Region r_work, r_desc;
     size_t ws_bytes = 0;
     char *ws = nullptr;
-    nsa::TileArgs *staging = nullptr;  // pinned host copy of the descriptors
-    hipEvent_t copied = nullptr;       // completion of the last descriptor upload
+    // pinned host staging: descriptors [cap_meshes] then the work table [cap_tiles] of (mesh, tile)
+    char *staging = nullptr;
+    size_t staging_desc = 0;             // byte offset of the work table in staging
+    hipEvent_t copied = nullptr;         // completion of the last upload from staging
+    bool work_dirty = false;             // work table changed since it was last copied
     bool inputs_set = false;
+    nsa::TileArgs *desc_host() { return (nsa::TileArgs *)staging; }
+    int2 *work_host() { return (int2 *)(staging + staging_desc); }
     ~nsa_batch() {
         // errors cannot be reported from a destructor; the handles are released either way
         if (copied) {
@@ -839,54 +863,50 @@ struct nsa_batch {
     }
 };
 
-extern "C" {
+namespace {
 
-nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out) {
-    if (!out || nmesh <= 0 || !meshes) return fail(NSA_EINVAL, "nsa_batch_create: bad arguments");
-    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
-    *out = nullptr;
-    int dev = -1;
+nsa_status check_members(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, int64_t *tiles, int *dev,
+                         int32_t *threads) {
+    *tiles = 0;
+    *dev = -1;
+    *threads = 0;
     for (int32_t i = 0; i < nmesh; i++) {
         const nsa_mesh *m = meshes[i];
         if (!m) return fail(NSA_EINVAL, "mesh %d is null", i);
         if (!m->ws) return fail(NSA_ESTATE, "mesh %d is not uploaded", i);
-        if (!m->plan[scatter].ok && m->nelem > 0)
-            return fail(NSA_EUNSUPPORTED, "mesh %d cannot use the tiled kernel", i);
-        if (i == 0) dev = m->device;
-        if (m->device != dev) return fail(NSA_EINVAL, "meshes are on different devices");
+        const nsa::TilePlan &P = m->plan[scatter];
+        if (!P.ok && m->nelem > 0) return fail(NSA_EUNSUPPORTED, "mesh %d cannot use the tiled kernel", i);
+        if (i == 0) *dev = m->device;
+        if (m->device != *dev) return fail(NSA_EINVAL, "meshes are on different devices");
+        if (P.ok) {
+            if (*threads && P.threads != *threads)
+                return fail(NSA_EUNSUPPORTED, "meshes planned for different workgroup sizes");
+            *threads = P.threads;
+        }
+        *tiles += P.ntiles();
     }
+    return NSA_OK;
+}
+
+nsa_status batch_alloc(int32_t cap_meshes, int64_t cap_tiles, int32_t scatter, int dev, nsa_batch **out) {
     nsa_batch *b = nullptr;
     try {
         b = new nsa_batch;
         b->scatter = scatter;
         b->device = dev;
-        b->meshes.assign(meshes, meshes + nmesh);
-        b->threads = meshes[0]->plan[scatter].threads;
-        for (int32_t i = 0; i < nmesh; i++) {
-            const nsa::TilePlan &P = meshes[i]->plan[scatter];
-            if (P.ok && P.threads != b->threads) {
-                delete b;
-                return fail(NSA_EUNSUPPORTED, "meshes planned for different workgroup sizes");
-            }
-            b->lds = std::max<int64_t>(b->lds, P.lds);
-            b->elements += meshes[i]->nelem;
-            for (int64_t t = 0; t < P.ntiles(); t++) b->work.push_back(make_int2(i, (int)t));
-        }
-        if (b->work.size() > (size_t)INT32_MAX) {
-            delete b;
-            return fail(NSA_EUNSUPPORTED, "too many tiles in one batch");
-        }
-        size_t off = 0;
-        b->r_work.off = 0;
-        b->r_work.bytes = std::max<size_t>(1, b->work.size()) * sizeof(int2);
-        off = align_up(b->r_work.bytes);
-        b->r_desc.off = off;
-        b->r_desc.bytes = (size_t)nmesh * sizeof(nsa::TileArgs);
-        b->ws_bytes = align_up(off + b->r_desc.bytes);
-        nsa_status st = hip_check(hipHostMalloc((void **)&b->staging, b->r_desc.bytes, hipHostMallocDefault),
+        b->cap_meshes = cap_meshes;
+        b->cap_tiles = cap_tiles;
+        b->r_desc.off = 0;
+        b->r_desc.bytes = (size_t)cap_meshes * sizeof(nsa::TileArgs);
+        b->r_work.off = align_up(b->r_desc.bytes);
+        b->r_work.bytes = std::max<size_t>(1, (size_t)cap_tiles) * sizeof(int2);
+        b->ws_bytes = align_up(b->r_work.off + b->r_work.bytes);
+        b->staging_desc = b->r_work.off;
+        nsa_status st = hip_check(hipHostMalloc((void **)&b->staging, b->ws_bytes, hipHostMallocDefault),
                                   "hipHostMalloc");
         if (!st) st = hip_check(hipEventCreateWithFlags(&b->copied, hipEventDisableTiming), "hipEventCreate");
-        if (!st) st = hip_check(hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev),
+        if (!st && dev < 0) st = hip_check(hipGetDevice(&b->device), "hipGetDevice");
+        if (!st) st = hip_check(hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device),
                                 "hipDeviceGetAttribute");
         if (st) {
             delete b;
@@ -894,10 +914,98 @@ nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_
         }
     } catch (const std::bad_alloc &) {
         delete b;
-        return fail(NSA_ENOMEM, "nsa_batch_create: host allocation failed");
+        return fail(NSA_ENOMEM, "batch: host allocation failed");
+    }
+    *out = b;
+    return NSA_OK;
+}
+
+// Install new members (already checked) and write their work table into the staging buffer.
+nsa_status batch_fill(nsa_batch *b, int32_t nmesh, const nsa_mesh *const *meshes, int32_t threads) {
+    // the staging buffer may still feed the previous upload
+    nsa_status st = hip_check(hipEventSynchronize(b->copied), "batch staging wait");
+    if (st) return st;
+    b->meshes.assign(meshes, meshes + nmesh);
+    b->threads = threads ? threads : kPlanThreads[b->scatter];
+    b->lds = 0;
+    b->elements = 0;
+    int2 *w = b->work_host();
+    int64_t n = 0;
+    for (int32_t i = 0; i < nmesh; i++) {
+        const nsa::TilePlan &P = meshes[i]->plan[b->scatter];
+        b->lds = std::max<int64_t>(b->lds, P.lds);
+        b->elements += meshes[i]->nelem;
+        for (int64_t t = 0; t < P.ntiles(); t++) w[n++] = make_int2(i, (int)t);
+    }
+    b->ntiles = n;
+    b->work_dirty = true;
+    b->inputs_set = false;
+    return NSA_OK;
+}
+
+// Copy the work table (if it changed) from staging into the workspace, stream-ordered.
+nsa_status batch_push_work(nsa_batch *b, hipStream_t s) {
+    if (!b->work_dirty) return NSA_OK;
+    if (b->ntiles > 0) {
+        nsa_status st = hip_check(hipMemcpyAsync(b->ws + b->r_work.off, b->work_host(), (size_t)b->ntiles * sizeof(int2),
+                                                 hipMemcpyHostToDevice, s), "batch work upload");
+        if (!st) st = hip_check(hipEventRecord(b->copied, s), "batch event");
+        if (st) return st;
+    }
+    b->work_dirty = false;
+    return NSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out) {
+    if (!out || nmesh <= 0 || !meshes) return fail(NSA_EINVAL, "nsa_batch_create: bad arguments");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    *out = nullptr;
+    int64_t tiles = 0;
+    int dev = -1;
+    int32_t threads = 0;
+    nsa_status st = check_members(nmesh, meshes, scatter, &tiles, &dev, &threads);
+    if (st) return st;
+    if (tiles > (int64_t)INT32_MAX) return fail(NSA_EUNSUPPORTED, "too many tiles in one batch");
+    nsa_batch *b = nullptr;
+    st = batch_alloc(nmesh, tiles, scatter, dev, &b);
+    if (st) return st;
+    st = batch_fill(b, nmesh, meshes, threads);
+    if (st) {
+        delete b;
+        return st;
     }
     *out = b;
     return ok();
+}
+
+nsa_status nsa_batch_reserve(int32_t max_meshes, int64_t max_tiles, int32_t scatter, nsa_batch **out) {
+    if (!out || max_meshes <= 0 || max_tiles <= 0) return fail(NSA_EINVAL, "nsa_batch_reserve: bad arguments");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    if (max_tiles > (int64_t)INT32_MAX) return fail(NSA_EUNSUPPORTED, "too many tiles in one batch");
+    *out = nullptr;
+    nsa_batch *b = nullptr;
+    nsa_status st = batch_alloc(max_meshes, max_tiles, scatter, -1, &b);
+    if (st) return st;
+    *out = b;
+    return ok();
+}
+
+nsa_status nsa_batch_reset(nsa_batch *b, int32_t nmesh, const nsa_mesh *const *meshes) {
+    if (!b || nmesh <= 0 || !meshes) return fail(NSA_EINVAL, "nsa_batch_reset: bad arguments");
+    if (nmesh > b->cap_meshes) return fail(NSA_ENOMEM, "%d meshes, capacity %d", nmesh, b->cap_meshes);
+    int64_t tiles = 0;
+    int dev = -1;
+    int32_t threads = 0;
+    nsa_status st = check_members(nmesh, meshes, b->scatter, &tiles, &dev, &threads);
+    if (st) return st;
+    if (dev != b->device) return fail(NSA_EINVAL, "meshes live on device %d, the batch on %d", dev, b->device);
+    if (tiles > b->cap_tiles) return fail(NSA_ENOMEM, "%lld tiles, capacity %lld", (long long)tiles, (long long)b->cap_tiles);
+    st = batch_fill(b, nmesh, meshes, threads);
+    return st ? st : ok();
 }
 
 nsa_status nsa_batch_destroy(nsa_batch *b) {
@@ -909,7 +1017,7 @@ nsa_status nsa_batch_get_info(const nsa_batch *b, size_t *ws_bytes, int64_t *nti
                               int32_t *lds_bytes) {
     if (!b) return fail(NSA_EINVAL, "nsa_batch_get_info: null batch");
     if (ws_bytes) *ws_bytes = b->ws_bytes;
-    if (ntiles) *ntiles = (int64_t)b->work.size();
+    if (ntiles) *ntiles = b->ntiles;
     if (nelem) *nelem = b->elements;
     if (lds_bytes) *lds_bytes = (int32_t)b->lds;
     return ok();
@@ -923,15 +1031,10 @@ nsa_status nsa_batch_upload(nsa_batch *b, void *ws, size_t ws_bytes, void *strea
     nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st) return st;
     if (dev != b->device) return fail(NSA_EINVAL, "batch meshes live on device %d, current is %d", b->device, dev);
-    hipStream_t s = (hipStream_t)stream;
     b->ws = (char *)ws;
-    if (!b->work.empty()) {
-        st = hip_check(hipMemcpyAsync(b->ws + b->r_work.off, b->work.data(), b->work.size() * sizeof(int2),
-                                      hipMemcpyHostToDevice, s), "batch upload");
-        if (st) return st;
-    }
-    st = hip_check(hipStreamSynchronize(s), "batch upload sync");
-    if (!st) st = hip_check(nsa::prepare_batch(b->threads, (size_t)b->lds), "batch LDS limit");
+    b->work_dirty = true;
+    st = batch_push_work(b, (hipStream_t)stream);
+    if (!st) st = hip_check(nsa::prepare_batch(b->threads, (size_t)kMaxTileLds), "batch LDS limit");
     return st ? st : ok();
 }
 
@@ -940,6 +1043,7 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
                                 void *stream) {
     if (!b || !vel || !rho || !mu || !dt || !values || !rhs) return fail(NSA_EINVAL, "nsa_batch_set_inputs: null argument");
     if (!b->ws) return fail(NSA_ESTATE, "nsa_batch_set_inputs before nsa_batch_upload");
+    if (b->meshes.empty()) return fail(NSA_ESTATE, "nsa_batch_set_inputs on a batch without members");
     if (accumulate != 0 && accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
     // the staging buffer may still feed the previous upload
     nsa_status st = hip_check(hipEventSynchronize(b->copied), "batch staging wait");
@@ -973,13 +1077,19 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
         t.threads = b->threads;
         t.values = values[i];
         t.rhs = rhs[i];
-        b->staging[i] = t;
+        b->desc_host()[i] = t;
     }
     hipStream_t s = (hipStream_t)stream;
-    st = hip_check(hipMemcpyAsync(b->ws + b->r_desc.off, b->staging, b->r_desc.bytes, hipMemcpyHostToDevice, s),
-                   "batch descriptor upload");
-    if (!st) st = hip_check(hipEventRecord(b->copied, s), "batch event");
+    st = hip_check(hipMemcpyAsync(b->ws + b->r_desc.off, b->staging, b->meshes.size() * sizeof(nsa::TileArgs),
+                                  hipMemcpyHostToDevice, s), "batch descriptor upload");
     if (st) return st;
+    if (b->work_dirty) {
+        st = batch_push_work(b, s);  // records the event after both copies
+        if (st) return st;
+    } else {
+        st = hip_check(hipEventRecord(b->copied, s), "batch event");
+        if (st) return st;
+    }
     b->inputs_set = true;
     return ok();
 }
@@ -994,7 +1104,7 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
     for (int r : o.reserved)
         if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
-    const int64_t total = (int64_t)b->work.size();
+    const int64_t total = b->ntiles;
     if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
     int64_t g = grid_wgs ? grid_wgs : (int64_t)b->ncu * (b->threads == 64 ? 4 : 2);
     g = std::min<int64_t>(g, (total + 7) / 8 * 8);

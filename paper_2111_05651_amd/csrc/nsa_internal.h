@@ -130,6 +130,7 @@ struct nsa_mesh {
     nsa::TilePlan plan[2];
     int32_t want_blocks[2] = {0, 0};
     bool planned = false;
+    bool keep_direct = true;            // upload the direct kernel's SoA arrays
     std::mutex plan_mu;
     // device layout (offsets into the caller's workspace)
     nsa::Region r_ln, r_coord, r_emap, r_ln_c, r_emap_c, r_coord4, r_bptr;

@@ -231,3 +231,26 @@ def served_sizes(nmesh: int = 200, seed: int = 5, tmin: float = 1e3, tmax: float
 def request_velocity(npoin: int, seed: int) -> np.ndarray:
     """Per-request velocity field: U[-1,1]^3 per node from the request seed."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(npoin, 3))
+
+
+def config_served(nmesh: int = 200, seed: int = 5, tmin: float = 1e3, tmax: float = 5e6):
+    """Resident meshes of the served workload: jittered cubes with the edge counts of served_sizes."""
+    out = []
+    for i, n in enumerate(served_sizes(nmesh, seed, tmin, tmax)):
+        out.append(make_mesh(n, jitter=True, velocity="zero", seed=seed * 100_003 + i, name=f"served{i}_n{n}"))
+    return out
+
+
+def served_requests(nreq: int, nmesh: int, rate: float, seed: int = 6):
+    """Open-loop request stream: Poisson arrivals at `rate` per second (times from 0), a uniformly
+    chosen resident mesh, rho ~ U[0.5, 2], mu log-uniform in [1e-4, 1e-2], dt ~ U[1e-3, 1e-2] and a
+    velocity seed per request."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    mesh = rng.integers(0, nmesh, size=nreq)
+    rho = rng.uniform(0.5, 2.0, size=nreq)
+    mu = 10.0 ** rng.uniform(-4.0, -2.0, size=nreq)
+    dt = rng.uniform(1e-3, 1e-2, size=nreq)
+    vseed = rng.integers(0, 2 ** 62, size=nreq)
+    return [dict(t=float(t[i]), mesh=int(mesh[i]), rho=float(rho[i]), mu=float(mu[i]), dt=float(dt[i]),
+                 vel_seed=int(vseed[i])) for i in range(nreq)]

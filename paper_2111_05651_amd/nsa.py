@@ -21,9 +21,9 @@ KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT = 0, 1, 2
 
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
-           "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
+           "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
-           "nsa_batch_create", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
+           "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
            "nsa_assemble_batched"]
 
 
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_pattern_fill.argtypes = [i64, i64, P, P, P, P]
     lib.nsa_mesh_create.argtypes = [i64, i64, P, P, C.POINTER(P)]
     lib.nsa_mesh_set_tiling.argtypes = [P, i32, i32]
+    lib.nsa_mesh_keep_direct.argtypes = [P, i32]
     lib.nsa_mesh_destroy.argtypes = [P]
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_release_host.argtypes = [P]
     lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
     lib.nsa_batch_create.argtypes = [i32, P, i32, C.POINTER(P)]
+    lib.nsa_batch_reserve.argtypes = [i32, i64, i32, C.POINTER(P)]
+    lib.nsa_batch_reset.argtypes = [P, i32, P]
     lib.nsa_batch_destroy.argtypes = [P]
     lib.nsa_batch_get_info.argtypes = [P, P, P, P, P]
     lib.nsa_batch_upload.argtypes = [P, P, sz, P]
@@ -128,7 +131,7 @@ class Mesh:
     """A registered mesh (host handle) and, after upload(), its device workspace (a torch tensor)."""
 
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
-                 tile_blocks_colour: int | None = None):
+                 tile_blocks_colour: int | None = None, keep_direct: bool = True):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -142,6 +145,8 @@ class Mesh:
             _check(lib.nsa_mesh_set_tiling(h, ATOMIC, int(tile_blocks)), "nsa_mesh_set_tiling")
         if tile_blocks_colour is not None:
             _check(lib.nsa_mesh_set_tiling(h, COLOUR, int(tile_blocks_colour)), "nsa_mesh_set_tiling")
+        if not keep_direct:
+            _check(lib.nsa_mesh_keep_direct(h, 0), "nsa_mesh_keep_direct")
         self.info = self._info()
 
     @classmethod
@@ -150,6 +155,10 @@ class Mesh:
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")
+        self.info = self._info()
+
+    def keep_direct(self, keep: bool):
+        _check(load().nsa_mesh_keep_direct(self._h, int(bool(keep))), "nsa_mesh_keep_direct")
         self.info = self._info()
 
     def _info(self) -> MeshInfo:
@@ -248,23 +257,48 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
 
 class Batch:
     """Many uploaded meshes assembled by one persistent launch (nsa_batch_*). Keeps references to
-    the meshes, its device workspace and the last inputs so that nothing it points at is freed."""
+    the meshes, its device workspace and the last inputs so that nothing it points at is freed.
 
-    def __init__(self, meshes, scatter=ATOMIC, device="cuda", stream=None):
+    Batch(meshes, ...) fixes its members; Batch.reserve(max_meshes, max_tiles, ...) makes an empty
+    reusable batch whose members are set per launch with reset()."""
+
+    def __init__(self, meshes=None, scatter=ATOMIC, device="cuda", stream=None, *, _capacity=None):
         import torch
         lib = load()
-        self.meshes = list(meshes)
         self.scatter = int(scatter)
-        arr = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
         h = C.c_void_p()
-        _check(lib.nsa_batch_create(len(self.meshes), arr, self.scatter, C.byref(h)), "nsa_batch_create")
+        if _capacity is None:
+            self.meshes = list(meshes)
+            arr = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
+            _check(lib.nsa_batch_create(len(self.meshes), arr, self.scatter, C.byref(h)), "nsa_batch_create")
+        else:
+            self.meshes = []
+            _check(lib.nsa_batch_reserve(int(_capacity[0]), int(_capacity[1]), self.scatter, C.byref(h)),
+                   "nsa_batch_reserve")
         self._h = h
-        ws, nt, ne, lds = C.c_size_t(), C.c_int64(), C.c_int64(), C.c_int32()
-        _check(lib.nsa_batch_get_info(h, C.byref(ws), C.byref(nt), C.byref(ne), C.byref(lds)), "nsa_batch_get_info")
-        self.ntiles, self.nelem, self.lds_bytes = nt.value, ne.value, lds.value
-        self.ws = torch.empty(int(ws.value), dtype=torch.uint8, device=device)
-        _check(lib.nsa_batch_upload(h, self.ws.data_ptr(), int(ws.value), _stream_handle(stream)), "nsa_batch_upload")
+        self._refresh()
+        self.ws = torch.empty(int(self.ws_bytes), dtype=torch.uint8, device=device)
+        _check(lib.nsa_batch_upload(h, self.ws.data_ptr(), int(self.ws_bytes), _stream_handle(stream)),
+               "nsa_batch_upload")
         self._keep = None
+
+    @classmethod
+    def reserve(cls, max_meshes, max_tiles, scatter=ATOMIC, device="cuda", stream=None):
+        return cls(None, scatter, device, stream, _capacity=(max_meshes, max_tiles))
+
+    def _refresh(self):
+        ws, nt, ne, lds = C.c_size_t(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(load().nsa_batch_get_info(self._h, C.byref(ws), C.byref(nt), C.byref(ne), C.byref(lds)),
+               "nsa_batch_get_info")
+        self.ws_bytes, self.ntiles, self.nelem, self.lds_bytes = ws.value, nt.value, ne.value, lds.value
+
+    def reset(self, meshes):
+        """New members (uploaded meshes; repeats allowed). Call set_inputs before the next launch."""
+        meshes = list(meshes)
+        arr = (C.c_void_p * len(meshes))(*[m._h.value for m in meshes])
+        _check(load().nsa_batch_reset(self._h, len(meshes), arr), "nsa_batch_reset")
+        self.meshes = meshes
+        self._refresh()
 
     def alloc_outputs(self, device="cuda"):
         return [m.alloc_outputs(device) for m in self.meshes]
