@@ -315,7 +315,9 @@ def main():
     ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8", "batch64", "serve"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
-    ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto"])
+    ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto", "gather"])
+    ap.add_argument("--tile-blocks-gather", type=int, default=512, help="blocks per tile of the gather plan")
+    ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
     ap.add_argument("--tile-blocks-colour", type=int, default=256, help="tile size of the colour-mode plan")
     ap.add_argument("--no-baseline-fp64", action="store_true", help="skip timing the FP64 kernel beside")
@@ -357,23 +359,32 @@ def main():
         return run_serve(args)
     prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
     scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
-    kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO}[args.kernel]
+    kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO,
+            "gather": nsa.KERNEL_GATHER}[args.kernel]
 
     t0 = time.perf_counter()
     m = make_workload(args.workload)
     log(f"workload {args.workload}: {m.nelem} tets, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=args.tile_blocks, tile_blocks_colour=args.tile_blocks_colour)
+    gather = kern == nsa.KERNEL_GATHER
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=0 if gather else args.tile_blocks,
+                                tile_blocks_colour=0 if gather else args.tile_blocks_colour,
+                                tile_blocks_gather=args.tile_blocks_gather if gather else 0,
+                                keep_direct=kern in (nsa.KERNEL_DIRECT, nsa.KERNEL_AUTO))
     mesh.upload("cuda:0")
     info = mesh.info
-    log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} tile_elems/nelem="
-        f"{info.tile_elems[scat] / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes[scat]}")
+    if gather:
+        log(f"mesh registered: nnzb={info.nnzb} gather tiles={info.gather_ntiles} records/nelem="
+            f"{info.gather_records / max(m.nelem, 1):.2f} lds={list(info.gather_lds_bytes)}")
+    else:
+        log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} tile_elems/nelem="
+            f"{info.tile_elems[scat] / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes[scat]}")
     vel = torch.from_numpy(m.velocity).to("cuda:0")
     values, rhs = mesh.alloc_outputs("cuda:0")
     stream = torch.cuda.current_stream()
 
     def step(p=prec):
         nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=p, scatter=scat, kernel=kern, values=values,
-                     rhs=rhs, stream=stream)
+                     rhs=rhs, stream=stream, block_threads=args.block_threads)
 
     ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
@@ -390,11 +401,17 @@ def main():
     nbytes = algorithmic_bytes(m.nelem, m.npoin, info.nnzb)
     launch_ms = statistics.fmean(per)
     achieved = nbytes / (launch_ms / 1e3) / 1e9
-    nthreads = info.tile_threads[scat]
-    kname = f"k_tiled<{'float' if prec == nsa.MIXED else 'double'},{nthreads}>"
-    tb = args.tile_blocks if scat == nsa.ATOMIC else args.tile_blocks_colour
+    rt = "float" if prec == nsa.MIXED else "double"
+    if gather:
+        nthreads = args.block_threads or info.gather_threads
+        kname = f"k_gather<{rt},{nthreads}>"
+        tb = args.tile_blocks_gather
+    else:
+        nthreads = args.block_threads or info.tile_threads[scat]
+        kname = f"k_tiled<{rt},{nthreads}>"
+        tb = args.tile_blocks if scat == nsa.ATOMIC else args.tile_blocks_colour
     key = f"{kname}@{args.workload}/tile{tb}"
-    traffic = traffic_for(key, nbytes) if kern == nsa.KERNEL_TILED else None
+    traffic = traffic_for(key, nbytes) if kern in (nsa.KERNEL_TILED, nsa.KERNEL_GATHER) else None
     line = {
         "metric": "elements assembled/s",
         "value": m.nelem / (ms / 1e3),

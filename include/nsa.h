@@ -71,6 +71,12 @@ typedef int32_t nsa_status;
                                   contributions to them in LDS and writes every block once */
 #define NSA_KERNEL_DIRECT 2    /* element per lane, scattering straight into the global arrays
                                   (zero-fill first unless accumulating); reference implementation */
+#define NSA_KERNEL_GATHER 3    /* gather tiles: each block is summed in registers by one lane from a
+                                  precomputed list of element contributions (element order) and
+                                  stored once; no atomics, bit-reproducible in either scatter mode */
+
+/* plan index of nsa_mesh_set_tiling beside the two scatter modes */
+#define NSA_GATHER_PLAN 2
 
 typedef struct nsa_options {
     int32_t precision;         /* NSA_FP64 or NSA_MIXED */
@@ -80,7 +86,7 @@ typedef struct nsa_options {
     int32_t block_threads;     /* threads per workgroup, 0 = default; direct kernel: 64..256 in
                                   steps of 64; tiled atomic mode: 64, 128 or 256 (default 256);
                                   ignored by the tiled colour mode (one wavefront per tile) */
-    int32_t kernel;            /* NSA_KERNEL_AUTO, NSA_KERNEL_TILED or NSA_KERNEL_DIRECT */
+    int32_t kernel;            /* NSA_KERNEL_AUTO, _TILED, _DIRECT or _GATHER */
     int32_t reserved[3];       /* must be zero */
 } nsa_options;
 
@@ -97,6 +103,13 @@ typedef struct nsa_mesh_info {
     int32_t tile_threads[2];   /* workgroup size of the plan */
     int32_t tile_max_colours[2]; /* largest number of tile-local colours */
     int32_t tile_lds_bytes[2]; /* LDS a workgroup uses (largest tile) */
+    /* gather plan (NSA_KERNEL_GATHER) */
+    int64_t gather_ntiles;     /* 0 if there is none */
+    int64_t gather_records;    /* sum over tiles of the elements each tile evaluates */
+    int64_t gather_pairs;      /* element contributions (16 per element) */
+    int32_t gather_tile_blocks;/* requested blocks per tile */
+    int32_t gather_threads;    /* workgroup size */
+    int32_t gather_lds_bytes[2]; /* LDS of the largest tile, [0] FP64, [1] mixed precision */
 } nsa_mesh_info;
 
 typedef struct nsa_mesh nsa_mesh; /* opaque */
@@ -146,6 +159,12 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
  * (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be called before nsa_mesh_upload
  * (NSA_ESTATE after). */
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks);
+/* With scatter = NSA_GATHER_PLAN the call sizes the gather plan instead, which is not built unless
+ * asked for: contiguous row ranges of at most tile_blocks blocks (64..4096; 0 drops the plan), 4095
+ * elements and 65535 element
+ * contributions, whose LDS (48 bytes per touched node, 376 per element with FP64 element data,
+ * 184 in mixed precision, 2 per contribution) stays within 80 KB in mixed precision and 160 KB in
+ * FP64. */
 /* Whether nsa_mesh_upload also stores the direct kernel's arrays (SoA connectivity, element-to-block
  * map and their colour-ordered copies, ~160 bytes per element; default 1). With 0 the mesh can only
  * be assembled by the tiled kernel (NSA_KERNEL_DIRECT returns NSA_EUNSUPPORTED). Before upload. */
@@ -171,6 +190,18 @@ nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_
 nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
                               int32_t *elems, int32_t *colours, int64_t *tile_nptr, int32_t *tile_nodes,
                               uint8_t *records);
+/* Gather plan (sizes from nsa_mesh_get_info; any array may be NULL): tile_row int32 [ntiles+1],
+ * tile_nptr int64 [ntiles+1] and tile_nodes int32 (node tables as for the row tiles), tile_eptr
+ * int64 [ntiles+1], elems int32 [gather_records] (element of each record, ascending inside a tile),
+ * local_nodes uint16 [gather_records][4] (the element's vertices as local node ids, in its own
+ * vertex order), tile_pptr int64 [ntiles+1], pairs uint16 [gather_pairs] (record << 4 | a << 2 | b:
+ * record adds its block (a, b) to the block being summed), slots uint32 [nnzb] (for tile t the
+ * entries at bptr[tile_row[t]] .. : local block index << 16 | offset of its pair list in the tile;
+ * a list ends where the next slot's begins, the last at the tile's pair count). NSA_EUNSUPPORTED
+ * without a gather plan. */
+nsa_status nsa_mesh_get_gather(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_nptr, int32_t *tile_nodes,
+                               int64_t *tile_eptr, int32_t *elems, uint16_t *local_nodes, int64_t *tile_pptr,
+                               uint16_t *pairs, uint32_t *slots);
 /* Make the mesh device-resident: copies the connectivity, coordinates, block maps, colour lists and
  * schedules into ws (device, at least info.ws_bytes bytes, 256-byte aligned, caller-owned and kept
  * alive while the mesh is used). Synchronous: returns after the copies completed on the stream. */

@@ -368,6 +368,170 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
     return NSA_OK;
 }
 
+// Gather tiles (see nsa_internal.h): contiguous row ranges grown while the tile stays within
+// tile_blocks blocks, 4095 elements, 65535 contributions, 80 KB of LDS in the mixed form (two
+// workgroups per CU) and 160 KB with FP64 element data. Records are the elements
+// touching the tile in ascending element id with the local ids of their vertices; every block's
+// contributions follow in record order; slots order the blocks by contribution count, descending.
+constexpr int32_t kGatherThreads = 256;
+constexpr int32_t kMaxGatherBlocks = 4096;
+constexpr int32_t kMaxGatherRecs = 4095;
+constexpr int64_t kMaxGatherPairs = 65535;
+constexpr int64_t kGatherLdsMixed = 80 * 1024;  // two workgroups per CU in the mixed form
+
+nsa_status build_gather(nsa_mesh *m, nsa::GatherPlan &P, int32_t tile_blocks, int32_t threads) {
+    P = nsa::GatherPlan();
+    P.tile_blocks = tile_blocks;
+    P.threads = threads;
+    const int64_t np = m->npoin;
+    if (np == 0) return NSA_OK;
+    std::vector<int64_t> n2e_ptr;
+    std::vector<int32_t> n2e;
+    node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
+    std::vector<int32_t> stamp(np, -1), estamp(m->nelem, -1);
+    P.row.push_back(0);
+    int32_t tid = 0;
+    for (int64_t r0 = 0; r0 < np; tid++) {
+        int64_t r1 = r0, nodes = 0, recs = 0, pairs = 0;
+        while (r1 < np) {
+            int64_t addn = 0, adde = 0;
+            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) addn += stamp[m->bcol[k]] != tid;
+            for (int64_t k = n2e_ptr[r1]; k < n2e_ptr[r1 + 1]; k++) adde += estamp[n2e[k]] != tid;
+            const int64_t addp = 4 * (n2e_ptr[r1 + 1] - n2e_ptr[r1]);
+            const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
+            const int32_t nn = (int32_t)(nodes + addn), nre = (int32_t)(recs + adde), npa = (int32_t)(pairs + addp);
+            const int64_t lds = nsa::gather_lds_bytes(nn, nre, npa, true);
+            const int64_t lds32 = nsa::gather_lds_bytes(nn, nre, npa, false);
+            const bool over = blocks > tile_blocks || lds > kMaxTileLds || lds32 > kGatherLdsMixed ||
+                              recs + adde > kMaxGatherRecs ||
+                              pairs + addp > kMaxGatherPairs || nodes + addn > 65535;
+            if (over && r1 > r0) break;
+            if (over) return NSA_OK;  // one row alone does not fit: no gather plan for this mesh
+            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
+            for (int64_t k = n2e_ptr[r1]; k < n2e_ptr[r1 + 1]; k++) estamp[n2e[k]] = tid;
+            nodes += addn;
+            recs += adde;
+            pairs += addp;
+            r1++;
+        }
+        P.row.push_back((int32_t)r1);
+        r0 = r1;
+    }
+    std::vector<int32_t>().swap(stamp);
+    std::vector<int32_t>().swap(estamp);
+    const int64_t nt = (int64_t)P.row.size() - 1;
+    P.slots.assign(m->nnzb, 0);
+    struct Out {
+        std::vector<int32_t> els, nodes;
+        std::vector<uint2> recs;
+        std::vector<uint16_t> pairs;
+        std::vector<int64_t> ecnt, ncnt, pcnt;
+        int32_t cap_blocks = 0, cap_recs = 0, cap_nodes = 0, cap_pairs = 0;
+        int64_t lds64 = 0, lds32 = 0;
+    };
+    std::vector<Out> outs(host_threads());
+    int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
+        Out &o = outs[ci];
+        std::vector<int32_t> els, other, cnt, order, start, fill;
+        std::vector<uint32_t> tmp;  // (record << 4 | a << 2 | b) per contribution, grouped by block
+        for (int64_t t = tb; t < te; t++) {
+            const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
+            const int64_t b0 = m->bptr[r0];
+            const int32_t nb = (int32_t)(m->bptr[r1] - b0);
+            els.clear();
+            for (int32_t i = r0; i < r1; i++) els.insert(els.end(), n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
+            std::sort(els.begin(), els.end());
+            els.erase(std::unique(els.begin(), els.end()), els.end());
+            other.clear();
+            for (int32_t e : els)
+                for (int a = 0; a < 4; a++) {
+                    const int32_t g = m->lnods[4 * (int64_t)e + a];
+                    if (g < r0 || g >= r1) other.push_back(g);
+                }
+            std::sort(other.begin(), other.end());
+            other.erase(std::unique(other.begin(), other.end()), other.end());
+            for (int32_t i = r0; i < r1; i++) o.nodes.push_back(i);
+            o.nodes.insert(o.nodes.end(), other.begin(), other.end());
+            const int32_t nnod = nr + (int32_t)other.size();
+            auto local = [&](int32_t g) -> uint32_t {
+                if (g >= r0 && g < r1) return (uint32_t)(g - r0);
+                return (uint32_t)(nr + (std::lower_bound(other.begin(), other.end(), g) - other.begin()));
+            };
+            // contributions per block, in record order
+            cnt.assign(nb, 0);
+            for (size_t ri = 0; ri < els.size(); ri++) {
+                const int64_t e = els[ri];
+                for (int a = 0; a < 4; a++) {
+                    const int32_t g = m->lnods[4 * e + a];
+                    if (g < r0 || g >= r1) continue;
+                    for (int b = 0; b < 4; b++) cnt[m->emap[16 * e + 4 * a + b] - b0]++;
+                }
+            }
+            start.assign(nb + 1, 0);
+            for (int32_t k = 0; k < nb; k++) start[k + 1] = start[k] + cnt[k];
+            const int32_t npair = start[nb];
+            tmp.assign(npair, 0);
+            fill.assign(start.begin(), start.end() - 1);
+            for (size_t ri = 0; ri < els.size(); ri++) {
+                const int64_t e = els[ri];
+                const int32_t *ln = &m->lnods[4 * e];
+                o.recs.push_back(make_uint2(local(ln[0]) | local(ln[1]) << 16, local(ln[2]) | local(ln[3]) << 16));
+                o.els.push_back((int32_t)e);
+                for (int a = 0; a < 4; a++) {
+                    if (ln[a] < r0 || ln[a] >= r1) continue;
+                    for (int b = 0; b < 4; b++)
+                        tmp[fill[m->emap[16 * e + 4 * a + b] - b0]++] = (uint32_t)ri << 4 | (uint32_t)a << 2 | (uint32_t)b;
+                }
+            }
+            // slots: longest lists first, then block order
+            order.resize(nb);
+            for (int32_t k = 0; k < nb; k++) order[k] = k;
+            std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cnt[x] > cnt[y]; });
+            int32_t off = 0;
+            for (int32_t sidx = 0; sidx < nb; sidx++) {
+                const int32_t k = order[sidx];
+                P.slots[b0 + sidx] = (uint32_t)k << 16 | (uint32_t)off;
+                for (int32_t q = start[k]; q < start[k + 1]; q++) o.pairs.push_back((uint16_t)tmp[q]);
+                off += cnt[k];
+            }
+            o.ecnt.push_back((int64_t)els.size());
+            o.ncnt.push_back(nnod);
+            o.pcnt.push_back(npair);
+            o.cap_blocks = std::max(o.cap_blocks, nb);
+            o.cap_recs = std::max(o.cap_recs, (int32_t)els.size());
+            o.cap_nodes = std::max(o.cap_nodes, nnod);
+            o.cap_pairs = std::max(o.cap_pairs, npair);
+            o.lds64 = std::max(o.lds64, nsa::gather_lds_bytes(nnod, (int32_t)els.size(), npair, true));
+            o.lds32 = std::max(o.lds32, nsa::gather_lds_bytes(nnod, (int32_t)els.size(), npair, false));
+        }
+    });
+    P.eptr.assign(1, 0);
+    P.nptr.assign(1, 0);
+    P.pptr.assign(1, 0);
+    for (int i = 0; i < used; i++) {
+        Out &o = outs[i];
+        for (size_t k = 0; k < o.ecnt.size(); k++) {
+            P.eptr.push_back(P.eptr.back() + o.ecnt[k]);
+            P.nptr.push_back(P.nptr.back() + o.ncnt[k]);
+            P.pptr.push_back(P.pptr.back() + o.pcnt[k]);
+        }
+        P.elems.insert(P.elems.end(), o.els.begin(), o.els.end());
+        P.nodes.insert(P.nodes.end(), o.nodes.begin(), o.nodes.end());
+        P.recs.insert(P.recs.end(), o.recs.begin(), o.recs.end());
+        P.pairs.insert(P.pairs.end(), o.pairs.begin(), o.pairs.end());
+        P.cap_blocks = std::max(P.cap_blocks, o.cap_blocks);
+        P.cap_recs = std::max(P.cap_recs, o.cap_recs);
+        P.cap_nodes = std::max(P.cap_nodes, o.cap_nodes);
+        P.cap_pairs = std::max(P.cap_pairs, o.cap_pairs);
+        P.lds[0] = std::max(P.lds[0], o.lds64);
+        P.lds[1] = std::max(P.lds[1], o.lds32);
+        o = Out();
+    }
+    if ((int64_t)P.eptr.size() != nt + 1) return fail(NSA_EUNSUPPORTED, "gather plan inconsistent");
+    P.ok = true;
+    return NSA_OK;
+}
+
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 void plan_layout(nsa_mesh *m) {
@@ -384,7 +548,7 @@ void plan_layout(nsa_mesh *m) {
     take(m->r_emap, d ? 16 * ne * sizeof(int32_t) : 0);
     take(m->r_ln_c, d ? 4 * ne * sizeof(int32_t) : 0);
     take(m->r_emap_c, d ? 16 * ne * sizeof(int32_t) : 0);
-    const bool t = m->plan[0].ok || m->plan[1].ok;
+    const bool t = m->plan[0].ok || m->plan[1].ok || m->gplan.ok;
     take(m->r_coord4, t ? 4 * np * sizeof(double) : 0);
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
     for (nsa::TilePlan &P : m->plan) {
@@ -394,6 +558,15 @@ void plan_layout(nsa_mesh *m) {
         take(P.r_nodes, P.ok ? P.nodes.size() * sizeof(int32_t) : 0);
         take(P.r_recs, P.ok ? P.recs.size() * sizeof(nsa::TileRec) : 0);
     }
+    nsa::GatherPlan &G = m->gplan;
+    take(G.r_row, G.ok ? G.row.size() * sizeof(int32_t) : 0);
+    take(G.r_nptr, G.ok ? G.nptr.size() * sizeof(int64_t) : 0);
+    take(G.r_nodes, G.ok ? G.nodes.size() * sizeof(int32_t) : 0);
+    take(G.r_eptr, G.ok ? G.eptr.size() * sizeof(int64_t) : 0);
+    take(G.r_recs, G.ok ? G.recs.size() * sizeof(uint2) : 0);
+    take(G.r_pptr, G.ok ? G.pptr.size() * sizeof(int64_t) : 0);
+    take(G.r_pairs, G.ok ? G.pairs.size() * sizeof(uint16_t) : 0);
+    take(G.r_slots, G.ok ? G.slots.size() * sizeof(uint32_t) : 0);
     m->ws_bytes = std::max<size_t>(off, 256);
 }
 
@@ -411,6 +584,12 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
             } else {
                 m->plan[k] = nsa::TilePlan();
             }
+        }
+        if (m->want_gather > 0) {
+            nsa_status st = build_gather(m, m->gplan, m->want_gather, kGatherThreads);
+            if (st) return st;
+        } else {
+            m->gplan = nsa::GatherPlan();
         }
         plan_layout(m);
     } catch (const std::bad_alloc &) {
@@ -445,7 +624,7 @@ const char *nsa_status_string(nsa_status st) {
 
 const char *nsa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t nsa_version(void) { return 100; }
+int32_t nsa_version(void) { return 200; }
 
 nsa_status nsa_pattern_count(int64_t npoin, int64_t nelem, const int32_t *lnods, int64_t *bptr,
                              int64_t *nnzb) {
@@ -538,6 +717,7 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
         st = colour_elements(m);
         m->want_blocks[0] = kDefaultTileBlocks[0];
         m->want_blocks[1] = kDefaultTileBlocks[1];
+        m->want_gather = 0;  // the gather plan is opt-in (nsa_mesh_set_tiling with NSA_GATHER_PLAN)
         if (st) {
             delete m;
             return st;
@@ -552,11 +732,20 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
 
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_set_tiling: null mesh");
-    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
-    if (tile_blocks != 0 && (tile_blocks < 64 || tile_blocks > kMaxTileBlocks))
-        return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d] (or 0)", tile_blocks, kMaxTileBlocks);
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR && scatter != NSA_GATHER_PLAN)
+        return fail(NSA_EINVAL, "unknown plan %d", scatter);
+    const int32_t cap = scatter == NSA_GATHER_PLAN ? kMaxGatherBlocks : kMaxTileBlocks;
+    if (tile_blocks != 0 && (tile_blocks < 64 || tile_blocks > cap))
+        return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d] (or 0)", tile_blocks, cap);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tiling after upload");
     std::lock_guard<std::mutex> g(m->plan_mu);
+    if (scatter == NSA_GATHER_PLAN) {
+        if (m->want_gather != tile_blocks || !m->planned) {
+            m->want_gather = tile_blocks;
+            m->planned = false;
+        }
+        return ok();
+    }
     if (m->want_blocks[scatter] != tile_blocks || !m->planned) {
         m->want_blocks[scatter] = tile_blocks;
         m->planned = false;
@@ -602,6 +791,14 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
         info->tile_max_colours[k] = P.max_colours;
         info->tile_lds_bytes[k] = P.ok ? (int32_t)P.lds : 0;
     }
+    const nsa::GatherPlan &G = m->gplan;
+    info->gather_ntiles = G.ntiles();
+    info->gather_records = G.ok ? G.eptr.back() : 0;
+    info->gather_pairs = G.ok ? G.pptr.back() : 0;
+    info->gather_tile_blocks = G.tile_blocks;
+    info->gather_threads = G.threads;
+    info->gather_lds_bytes[0] = G.ok ? (int32_t)G.lds[0] : 0;
+    info->gather_lds_bytes[1] = G.ok ? (int32_t)G.lds[1] : 0;
     return ok();
 }
 
@@ -642,6 +839,27 @@ nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_
     return ok();
 }
 
+nsa_status nsa_mesh_get_gather(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_nptr, int32_t *tile_nodes,
+                               int64_t *tile_eptr, int32_t *elems, uint16_t *local_nodes, int64_t *tile_pptr,
+                               uint16_t *pairs, uint32_t *slots) {
+    if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_gather: null mesh");
+    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    nsa_status st = ensure_plans(m);
+    if (st) return st;
+    const nsa::GatherPlan &G = m->gplan;
+    if (!G.ok) return fail(NSA_EUNSUPPORTED, "no gather plan for this mesh");
+    if (tile_row) std::copy(G.row.begin(), G.row.end(), tile_row);
+    if (tile_nptr) std::copy(G.nptr.begin(), G.nptr.end(), tile_nptr);
+    if (tile_nodes) std::copy(G.nodes.begin(), G.nodes.end(), tile_nodes);
+    if (tile_eptr) std::copy(G.eptr.begin(), G.eptr.end(), tile_eptr);
+    if (elems) std::copy(G.elems.begin(), G.elems.end(), elems);
+    if (local_nodes) std::memcpy(local_nodes, G.recs.data(), G.recs.size() * sizeof(uint2));
+    if (tile_pptr) std::copy(G.pptr.begin(), G.pptr.end(), tile_pptr);
+    if (pairs) std::copy(G.pairs.begin(), G.pairs.end(), pairs);
+    if (slots) std::copy(G.slots.begin(), G.slots.end(), slots);
+    return ok();
+}
+
 nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream) {
     if (!m || !ws) return fail(NSA_EINVAL, "nsa_mesh_upload: null argument");
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
@@ -671,7 +889,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
             for (int64_t i = 0; i < np; i++)
                 for (int c = 0; c < 3; c++) co[c * np + i] = m->coord[3 * i + c];
         std::vector<double> co4;
-        if (m->plan[0].ok || m->plan[1].ok) {
+        if (m->plan[0].ok || m->plan[1].ok || m->gplan.ok) {
             co4.assign(4 * (size_t)np, 0.0);
             for (int64_t i = 0; i < np; i++)
                 for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
@@ -680,13 +898,17 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         nsa_status st;
         struct Up { const nsa::Region &r; const void *src; };
         const nsa::TilePlan &P0 = m->plan[0], &P1 = m->plan[1];
+        const nsa::GatherPlan &G = m->gplan;
         const Up ups[] = {{m->r_ln, ln.data()}, {m->r_coord, co.data()}, {m->r_emap, em.data()},
                           {m->r_ln_c, lnc.data()}, {m->r_emap_c, emc.data()},
                           {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
                           {P0.r_row, P0.row.data()}, {P0.r_eptr, P0.eptr.data()}, {P0.r_nptr, P0.nptr.data()},
                           {P0.r_nodes, P0.nodes.data()}, {P0.r_recs, P0.recs.data()},
                           {P1.r_row, P1.row.data()}, {P1.r_eptr, P1.eptr.data()}, {P1.r_nptr, P1.nptr.data()},
-                          {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()}};
+                          {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()},
+                          {G.r_row, G.row.data()}, {G.r_nptr, G.nptr.data()}, {G.r_nodes, G.nodes.data()},
+                          {G.r_eptr, G.eptr.data()}, {G.r_recs, G.recs.data()}, {G.r_pptr, G.pptr.data()},
+                          {G.r_pairs, G.pairs.data()}, {G.r_slots, G.slots.data()}};
         for (const Up &u : ups) {
             if (!u.r.bytes) continue;
             st = hip_check(hipMemcpyAsync(w + u.r.off, u.src, u.r.bytes, hipMemcpyHostToDevice, s),
@@ -714,6 +936,14 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m) {
     std::vector<int32_t>().swap(m->bcol);
     std::vector<int32_t>().swap(m->emap);
     std::vector<int32_t>().swap(m->colour_elems);
+    {
+        nsa::GatherPlan &G = m->gplan;
+        std::vector<int32_t>().swap(G.elems);
+        std::vector<int32_t>().swap(G.nodes);
+        std::vector<uint2>().swap(G.recs);
+        std::vector<uint16_t>().swap(G.pairs);
+        std::vector<uint32_t>().swap(G.slots);
+    }
     for (nsa::TilePlan &P : m->plan) {
         std::vector<int32_t>().swap(P.elems);
         std::vector<int32_t>().swap(P.colour);
@@ -737,14 +967,22 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
     if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
     for (int r : o.reserved)
         if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
-    if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED && o.kernel != NSA_KERNEL_DIRECT)
+    if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED && o.kernel != NSA_KERNEL_DIRECT &&
+        o.kernel != NSA_KERNEL_GATHER)
         return fail(NSA_EINVAL, "unknown kernel %d", o.kernel);
     const nsa::TilePlan &P = m->plan[o.scatter];
+    const nsa::GatherPlan &G = m->gplan;
     if (o.kernel == NSA_KERNEL_TILED && !P.ok)
         return fail(NSA_EUNSUPPORTED, "this mesh cannot use the tiled kernel (row degree > 256 or no plan)");
+    if (o.kernel == NSA_KERNEL_GATHER && !G.ok)
+        return fail(NSA_EUNSUPPORTED, "this mesh has no gather plan");
     int threads = o.block_threads ? o.block_threads : 256;
-    if (threads < 64 || threads > 256 || threads % 64)
+    if (o.kernel == NSA_KERNEL_GATHER) {
+        if (threads != 256 && threads != 512)
+            return fail(NSA_EINVAL, "block_threads %d: the gather kernel takes 256 or 512", threads);
+    } else if (threads < 64 || threads > 256 || threads % 64) {
         return fail(NSA_EINVAL, "block_threads %d not a multiple of 64 in [64, 256]", threads);
+    }
     if (!(rho > 0.0) || !std::isfinite(rho) || !(mu >= 0.0) || !std::isfinite(mu) || !(dt > 0.0) ||
         !std::isfinite(dt))
         return fail(NSA_EINVAL, "need rho > 0, mu >= 0, dt > 0 (finite); got %g %g %g", rho, mu, dt);
@@ -759,6 +997,32 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         return fail(NSA_EINVAL, "mesh uploaded on device %d, current device is %d", m->device, dev);
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.precision == NSA_MIXED;
+    if (o.kernel == NSA_KERNEL_GATHER) {
+        nsa::GatherArgs a;
+        a.ntiles = G.ntiles();
+        a.lds_bytes = G.lds[mixed ? 1 : 0];
+        a.tile_row = (const int32_t *)(m->ws + G.r_row.off);
+        a.tile_nptr = (const int64_t *)(m->ws + G.r_nptr.off);
+        a.tile_nodes = (const int32_t *)(m->ws + G.r_nodes.off);
+        a.tile_eptr = (const int64_t *)(m->ws + G.r_eptr.off);
+        a.rec = (const uint2 *)(m->ws + G.r_recs.off);
+        a.tile_pptr = (const int64_t *)(m->ws + G.r_pptr.off);
+        a.pairs = (const uint16_t *)(m->ws + G.r_pairs.off);
+        a.slot = (const uint32_t *)(m->ws + G.r_slots.off);
+        a.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
+        a.coord = (const double4 *)(m->ws + m->r_coord4.off);
+        a.vel = vel;
+        a.rho = rho;
+        a.mu = mu;
+        a.dt = dt;
+        a.accumulate = o.accumulate;
+        a.threads = o.block_threads ? o.block_threads : G.threads;
+        a.values = values;
+        a.rhs = rhs;
+        st = hip_check(nsa::launch_gather(mixed ? nsa::TileKern::Mixed : nsa::TileKern::F64, a, s),
+                       "assemble (gather)");
+        return st ? st : ok();
+    }
     if (o.kernel != NSA_KERNEL_DIRECT && P.ok) {
         nsa::TileArgs t;
         t.ntiles = P.ntiles();

@@ -91,6 +91,73 @@ hipError_t prepare_batch(int threads, size_t lds);
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
                               int64_t lds, int grid_wgs, hipStream_t s);
 
+hipError_t ensure_lds(const void *kern, size_t bytes);
+
+// Gather tiles. Tile t owns the contiguous block rows [row[t], row[t+1]) as in the row tiles above,
+// with the same node table (owned rows first). Its elements are records rec[eptr[t] .. eptr[t+1])
+// holding the four local node ids in the element's own vertex order (uint16 each), sorted by
+// element id. Every owned block is a list of contributions (record r, vertices a, b): element r
+// adds its 4x4 block (a, b) there. The lists sit in pairs[pptr[t] ..] as uint16 r << 4 | a << 2 | b,
+// each list in record order; the tile's blocks are visited in slot order, slot[bptr[row[t]] + s] =
+// local block index << 16 | offset of its list in the tile's pairs (a list ends where the next
+// slot's begins, the last one at the tile's pair count). Slots run from long lists to short ones so
+// that the lanes of one wavefront loop over lists of similar length.
+struct GatherArgs {
+    int64_t ntiles = 0;
+    int64_t lds_bytes = 0;
+    const int32_t *tile_row = nullptr;   // [ntiles+1]
+    const int64_t *tile_nptr = nullptr;  // [ntiles+1]
+    const int32_t *tile_nodes = nullptr;
+    const int64_t *tile_eptr = nullptr;  // [ntiles+1]
+    const uint2 *rec = nullptr;          // local node ids, 4 x uint16
+    const int64_t *tile_pptr = nullptr;  // [ntiles+1]
+    const uint16_t *pairs = nullptr;
+    const uint32_t *slot = nullptr;      // [nnzb]
+    const int64_t *bptr = nullptr;
+    const double4 *coord = nullptr;
+    const double *vel = nullptr;
+    double rho = 1, mu = 0, dt = 1;
+    int32_t accumulate = 0;
+    int32_t threads = 256;
+    double *values = nullptr;
+    double *rhs = nullptr;
+};
+
+// LDS of a gather tile: node table (6 doubles per node), the per-element data (kGatherRecF32 floats
+// or kGatherRecF64 doubles per record; odd multiples of 16 bytes so that the records of the lanes of
+// one 16-byte read spread over the banks), the records' local node ids (8 bytes each), then the
+// tile's contribution lists (2 bytes each).
+constexpr int kGatherRecF32 = 44;
+constexpr int kGatherRecF64 = 46;
+__host__ __device__ constexpr int64_t gather_elem_off(int32_t nnod) { return (48 * (int64_t)nnod + 15) & ~int64_t(15); }
+__host__ __device__ constexpr int64_t gather_rec_bytes(bool f64) { return f64 ? 8 * kGatherRecF64 : 4 * kGatherRecF32; }
+__host__ __device__ constexpr int64_t gather_loc_off(int32_t nnod, int32_t nrec, bool f64) {
+    return gather_elem_off(nnod) + (int64_t)nrec * gather_rec_bytes(f64);
+}
+__host__ __device__ constexpr int64_t gather_pair_off(int32_t nnod, int32_t nrec, bool f64) {
+    return gather_loc_off(nnod, nrec, f64) + 8 * (int64_t)nrec;
+}
+__host__ __device__ constexpr int64_t gather_lds_bytes(int32_t nnod, int32_t nrec, int32_t npair, bool f64) {
+    return gather_pair_off(nnod, nrec, f64) + ((2 * (int64_t)npair + 15) & ~int64_t(15));
+}
+hipError_t launch_gather(TileKern k, const GatherArgs &a, hipStream_t s);
+
+struct GatherPlan {
+    int32_t tile_blocks = 0;
+    int32_t threads = 256;
+    bool ok = false;
+    int64_t lds[2] = {0, 0};      // LDS of the largest tile: [0] FP64 element data, [1] mixed (FP32)
+    int32_t cap_blocks = 0, cap_recs = 0, cap_nodes = 0, cap_pairs = 0;
+    std::vector<int32_t> row;     // [ntiles+1]
+    std::vector<int64_t> nptr, eptr, pptr;
+    std::vector<int32_t> nodes, elems;
+    std::vector<uint2> recs;
+    std::vector<uint16_t> pairs;
+    std::vector<uint32_t> slots;  // [nnzb]
+    Region r_row, r_nptr, r_nodes, r_eptr, r_recs, r_pptr, r_pairs, r_slots;
+    int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
+};
+
 // A row-tile plan for one scatter mode (host copy, then device regions after upload).
 struct TilePlan {
     int32_t tile_blocks = 0;     // requested tile size: LDS budget tile_blocks * 160 bytes
@@ -129,6 +196,8 @@ struct nsa_mesh {
     // need (info, tiles, upload) from the requested sizes (0 = no plan for that mode)
     nsa::TilePlan plan[2];
     int32_t want_blocks[2] = {0, 0};
+    nsa::GatherPlan gplan;              // gather tiles (both scatter modes, both precisions)
+    int32_t want_gather = 0;
     bool planned = false;
     bool keep_direct = true;            // upload the direct kernel's SoA arrays
     std::mutex plan_mu;

@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 
+#include "nsa_device.h"
 #include "nsa_internal.h"
 
 namespace nsa {
@@ -269,59 +270,6 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 // instruction rarely target the same block.
 // ================================================================================================
 namespace {
-
-// Reciprocal: hardware estimate refined by two Newton steps (full FP64 accuracy for normal x).
-__device__ __forceinline__ double fast_rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return r;
-}
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// x^(-1/3) for x > 0: FP32 estimate (2^(-log2(x)/3)) refined by Newton steps r += r (1 - x r^3) / 3.
-__device__ __forceinline__ double rcbrt(double x) {
-    if (!(x > 1e-30 && x < 1e30)) return 1.0 / cbrt(x);  // outside the FP32 estimate's range
-    float xf = (float)x;
-    double r = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * (1.0f / 3.0f));
-#pragma unroll
-    for (int it = 0; it < 3; it++) r = fma(r * (1.0 / 3.0), fma(-x * r, r * r, 1.0), r);
-    return r;
-}
-
-// Geometry in FP64: grad N_a, V, h = (6V)^(1/3) = |det|^(1/3) and 1/h.
-struct Geo2 {
-    double G[4][3];
-    double V, h, rh;
-};
-
-__device__ __forceinline__ void geometry2(const double X[4][3], Geo2 &g) {
-    double J[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int s = 0; s < 3; s++) J[r][s] = X[s + 1][r] - X[0][r];
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const double inv = fast_rcp(det);
-    g.G[1][0] = c00 * inv; g.G[1][1] = c10 * inv; g.G[1][2] = c20 * inv;
-    g.G[2][0] = c01 * inv; g.G[2][1] = c11 * inv; g.G[2][2] = c21 * inv;
-    g.G[3][0] = c02 * inv; g.G[3][1] = c12 * inv; g.G[3][2] = c22 * inv;
-#pragma unroll
-    for (int d = 0; d < 3; d++) g.G[0][d] = -(g.G[1][d] + g.G[2][d] + g.G[3][d]);
-    const double adet = fabs(det);
-    g.V = adet * (1.0 / 6.0);
-    g.rh = rcbrt(adet);
-    g.h = adet * g.rh * g.rh;
-}
 
 // Element state in the integration precision R, for the closed-form integrals of the header.
 template <typename R>
@@ -599,7 +547,7 @@ size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
 }
 
 // Raise a kernel's dynamic-LDS limit once (not at every launch, so launches can be captured).
-static hipError_t ensure_lds(const void *kern, size_t bytes) {
+hipError_t ensure_lds(const void *kern, size_t bytes) {
     static std::mutex mu;
     static std::map<const void *, size_t> done;
     std::lock_guard<std::mutex> g(mu);

@@ -17,12 +17,13 @@ NSA_OK, NSA_EINVAL, NSA_ERANGE, NSA_EDEGENERATE, NSA_ENOMEM, NSA_EHIP, NSA_EUNSU
     0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 ATOMIC, COLOUR = 0, 1
-KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT = 0, 1, 2
+KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT, KERNEL_GATHER = 0, 1, 2, 3
+GATHER_PLAN = 2
 
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
-           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
+           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
            "nsa_assemble_batched"]
 
@@ -43,7 +44,9 @@ class MeshInfo(C.Structure):
                 ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64),
                 ("ntiles", C.c_int64 * 2), ("tile_elems", C.c_int64 * 2), ("tile_blocks", C.c_int32 * 2),
                 ("tile_threads", C.c_int32 * 2), ("tile_max_colours", C.c_int32 * 2),
-                ("tile_lds_bytes", C.c_int32 * 2)]
+                ("tile_lds_bytes", C.c_int32 * 2), ("gather_ntiles", C.c_int64), ("gather_records", C.c_int64),
+                ("gather_pairs", C.c_int64), ("gather_tile_blocks", C.c_int32), ("gather_threads", C.c_int32),
+                ("gather_lds_bytes", C.c_int32 * 2)]
 
 
 _lib = None
@@ -73,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
     lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
     lib.nsa_mesh_get_tiles.argtypes = [P, i32, P, P, P, P, P, P, P]
+    lib.nsa_mesh_get_gather.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
     lib.nsa_mesh_release_host.argtypes = [P]
     lib.nsa_assemble.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P]
@@ -131,7 +135,8 @@ class Mesh:
     """A registered mesh (host handle) and, after upload(), its device workspace (a torch tensor)."""
 
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
-                 tile_blocks_colour: int | None = None, keep_direct: bool = True):
+                 tile_blocks_colour: int | None = None, keep_direct: bool = True,
+                 tile_blocks_gather: int | None = None):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -145,13 +150,16 @@ class Mesh:
             _check(lib.nsa_mesh_set_tiling(h, ATOMIC, int(tile_blocks)), "nsa_mesh_set_tiling")
         if tile_blocks_colour is not None:
             _check(lib.nsa_mesh_set_tiling(h, COLOUR, int(tile_blocks_colour)), "nsa_mesh_set_tiling")
+        if tile_blocks_gather is not None:
+            _check(lib.nsa_mesh_set_tiling(h, GATHER_PLAN, int(tile_blocks_gather)), "nsa_mesh_set_tiling")
         if not keep_direct:
             _check(lib.nsa_mesh_keep_direct(h, 0), "nsa_mesh_keep_direct")
         self.info = self._info()
 
     @classmethod
-    def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None) -> "Mesh":
-        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour)
+    def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None,
+                    tile_blocks_gather: int | None = None, keep_direct: bool = True) -> "Mesh":
+        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather)
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")
@@ -209,6 +217,25 @@ class Mesh:
         _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), _ptr(out["tile_row"]), _ptr(out["tile_eptr"]),
                                       _ptr(out["elems"]), _ptr(out["colours"]), None, _ptr(out["tile_nodes"]),
                                       _ptr(out["records"])), "nsa_mesh_get_tiles")
+        return out
+
+    def gather(self):
+        """Gather plan: dict of tile_row, tile_nptr, tile_nodes, tile_eptr, elems, local_nodes
+        (uint16 [records][4]), tile_pptr, pairs (uint16) and slots (uint32 [nnzb])."""
+        i = self.info
+        nt, nr, npr = i.gather_ntiles, i.gather_records, i.gather_pairs
+        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_nptr=np.zeros(nt + 1, np.int64),
+                   tile_eptr=np.zeros(nt + 1, np.int64), elems=np.zeros(nr, np.int32),
+                   local_nodes=np.zeros((nr, 4), np.uint16), tile_pptr=np.zeros(nt + 1, np.int64),
+                   pairs=np.zeros(npr, np.uint16), slots=np.zeros(self.nnzb, np.uint32))
+        lib = load()
+        _check(lib.nsa_mesh_get_gather(self._h, None, _ptr(out["tile_nptr"]), None, None, None, None, None, None,
+                                       None), "nsa_mesh_get_gather")
+        out["tile_nodes"] = np.zeros(int(out["tile_nptr"][-1]), np.int32)
+        _check(lib.nsa_mesh_get_gather(self._h, _ptr(out["tile_row"]), None, _ptr(out["tile_nodes"]),
+                                       _ptr(out["tile_eptr"]), _ptr(out["elems"]), _ptr(out["local_nodes"]),
+                                       _ptr(out["tile_pptr"]), _ptr(out["pairs"]), _ptr(out["slots"])),
+               "nsa_mesh_get_gather")
         return out
 
     def upload(self, device="cuda", stream=None):

@@ -44,7 +44,20 @@ SMALL = {"cube8": inputs.config_small,
          "cube5_rcm": lambda: inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=18),
          "cube3": lambda: inputs.make_mesh(3, jitter=True, velocity="uniform", seed=19, rho=1.7, mu=3e-2, dt=2e-3)}
 KERNELS = [("direct", nsa.KERNEL_DIRECT, None), ("tiled64", nsa.KERNEL_TILED, 64),
-           ("tiled_default", nsa.KERNEL_TILED, None), ("tiled1024", nsa.KERNEL_TILED, 1024)]
+           ("tiled_default", nsa.KERNEL_TILED, None), ("tiled1024", nsa.KERNEL_TILED, 1024),
+           ("gather64", nsa.KERNEL_GATHER, 64), ("gather320", nsa.KERNEL_GATHER, 320),
+           ("gather4096_512thr", nsa.KERNEL_GATHER, 4096)]
+
+
+def mesh_for(m, kern):
+    """Mesh with the plan a KERNELS entry asks for."""
+    if kern[1] == nsa.KERNEL_GATHER:
+        return nsa.Mesh.from_inputs(m, tile_blocks_gather=kern[2]).upload()
+    return nsa.Mesh.from_inputs(m, tile_blocks=kern[2], tile_blocks_colour=kern[2]).upload()
+
+
+def kernel_kw(kern):
+    return dict(block_threads=512) if kern[0].endswith("512thr") else {}
 
 
 @pytest.mark.parametrize("cfg", list(SMALL))
@@ -54,19 +67,19 @@ def test_small_meshes(cfg, kern, mode):
     m = SMALL[cfg]()
     say(f"[parity] {cfg} nelem={m.nelem} kernel={kern[0]} mode={mode}")
     ref_v, ref_r = oracle.assemble(m)
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=kern[2], tile_blocks_colour=kern[2]).upload()
-    v, r = gpu_assemble(mesh, m, *mode, kernel=kern[1])
+    mesh = mesh_for(m, kern)
+    v, r = gpu_assemble(mesh, m, *mode, kernel=kern[1], **kernel_kw(kern))
     assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"{cfg} {kern[0]} {mode}")
 
 
 def test_degenerate_parameters():
     """mu = 0 with zero velocity (pure mass/Laplacian), huge and tiny dt, zero velocity RHS."""
     m = inputs.make_mesh(4, jitter=True, permute=True, seed=23)
-    mesh = nsa.Mesh.from_inputs(m).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
     for rho, mu, dt, vel in ((1.0, 0.0, 1e-2, np.zeros_like(m.velocity)), (2.0, 1e-3, 1e6, m.velocity),
                              (0.5, 1e-1, 1e-9, m.velocity), (1.0, 1e-3, 1e-2, np.zeros_like(m.velocity))):
         ref_v, ref_r = oracle.assemble(m, rho=rho, mu=mu, dt=dt, velocity=vel)
-        for mode in MODES + [(p, s_, nsa.KERNEL_DIRECT) for p, s_ in MODES]:
+        for mode in MODES + [(p, s_, k) for p, s_ in MODES for k in (nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER)]:
             v, r = gpu_assemble(mesh, m, *mode, vel=vel, rho=rho, mu=mu, dt=dt)
             err = class_errors(v, ref_v, r, ref_r)
             for k, e in err.items():
@@ -79,12 +92,12 @@ def test_degenerate_parameters():
 def test_accumulate():
     m = inputs.make_mesh(4, jitter=True, permute=True, seed=24)
     ref_v, ref_r = oracle.assemble(m)
-    mesh = nsa.Mesh.from_inputs(m).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
     vel = torch.from_numpy(m.velocity).cuda()
     values, rhs = mesh.alloc_outputs()
     values.fill_(1.0)
     rhs.fill_(-2.0)
-    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER):
         for scatter in (nsa.ATOMIC, nsa.COLOUR):
             values.fill_(1.0)
             rhs.fill_(-2.0)
@@ -98,8 +111,8 @@ def test_accumulate():
 
 def test_colour_path_bit_reproducible():
     m = inputs.make_mesh(12, jitter=True, permute=True, velocity="vortex", seed=25)
-    mesh = nsa.Mesh.from_inputs(m).upload()
-    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER):
         for prec in (nsa.FP64, nsa.MIXED):
             v0, r0 = gpu_assemble(mesh, m, prec, nsa.COLOUR, kernel=kernel)
             for _ in range(9):
@@ -111,7 +124,7 @@ def test_colour_path_reproducible_under_load():
     """Bit-identical results while another stream keeps the GPU busy (different wave interleavings),
     and across different launch streams."""
     m = inputs.make_mesh(20, jitter=True, permute=True, velocity="vortex", seed=27)
-    mesh = nsa.Mesh.from_inputs(m).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
     vel = torch.from_numpy(m.velocity).cuda()
     v0, r0 = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, scatter=nsa.COLOUR)
     torch.cuda.synchronize()
@@ -139,8 +152,8 @@ def test_empty_and_tiny():
     assert values.numel() == 0 and torch.all(rhs == 0)
     m = inputs.make_mesh(1, jitter=True, seed=26)           # 6 tets
     ref_v, ref_r = oracle.assemble(m)
-    mesh = nsa.Mesh.from_inputs(m).upload()
-    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER):
         for mode in MODES:
             v, r = gpu_assemble(mesh, m, *mode, kernel=kernel)
             assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"one hex {mode} kernel={kernel}")
@@ -153,10 +166,10 @@ def test_cube64_full(scatter):
     say(f"[parity] cube64 nelem={m.nelem} scatter={scatter}: oracle ...")
     pat = oracle.pattern(m.npoin, m.lnods)
     ref_v, ref_r = oracle.assemble(m, pat)
-    mesh = nsa.Mesh.from_inputs(m).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320).upload()
     bptr, bcol, emap = mesh.pattern()
     assert np.array_equal(bptr, pat[0]) and np.array_equal(bcol, pat[1]) and np.array_equal(emap, pat[2])
-    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT):
+    for kernel in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER):
         for prec in (nsa.FP64, nsa.MIXED):
             say(f"[parity] cube64 kernel={kernel} precision={prec} scatter={scatter}")
             v, r = gpu_assemble(mesh, m, prec, scatter, kernel=kernel)
@@ -171,13 +184,14 @@ def test_cube128_sampled(precision):
     row, plus the colour path on the same rows."""
     m = inputs.config_128()
     say(f"[parity] cube128 nelem={m.nelem} precision={precision}")
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512).upload()
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512, tile_blocks_gather=320).upload()
     rng = np.random.default_rng(128)
     rows = np.unique(np.concatenate([rng.choice(m.npoin, 190, replace=False), [0, 1, m.npoin - 2, m.npoin - 1]]))
     cols, deg, ov, orr = oracle.assemble_rows(m, rows, maxdeg=64)
     bptr, bcol, _ = mesh.pattern()
-    for scatter in (nsa.ATOMIC, nsa.COLOUR):
-        v, r = gpu_assemble(mesh, m, precision, scatter, kernel=nsa.KERNEL_TILED)
+    for scatter, kernel in ((nsa.ATOMIC, nsa.KERNEL_TILED), (nsa.COLOUR, nsa.KERNEL_TILED),
+                           (nsa.ATOMIC, nsa.KERNEL_GATHER)):
+        v, r = gpu_assemble(mesh, m, precision, scatter, kernel=kernel)
         got, ref = [], []
         for s, i in enumerate(rows):
             lo, hi = bptr[i], bptr[i + 1]
@@ -185,5 +199,20 @@ def test_cube128_sampled(precision):
             got.append(v[lo:hi])
             ref.append(ov[s, :deg[s]])
         err = assert_parity(np.concatenate(got), np.concatenate(ref), r[rows], orr, tol_of(precision),
-                            f"cube128 sampled precision={precision} scatter={scatter}")
+                            f"cube128 sampled precision={precision} scatter={scatter} kernel={kernel}")
         say(f"[parity] cube128 sampled errors {err}")
+
+
+def test_gather_bitwise_independent_of_tiling_and_mode():
+    """Each block is summed in element order whatever the tile size, the workgroup size or the
+    scatter mode: all of them give the same bits."""
+    m = inputs.make_mesh(10, jitter=True, permute=True, velocity="vortex", seed=29)
+    for prec in (nsa.FP64, nsa.MIXED):
+        base = None
+        for tb, nt in ((64, 256), (512, 256), (4096, 512), (300, 512)):
+            mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=tb).upload()
+            for scatter in (nsa.ATOMIC, nsa.COLOUR):
+                v, r = gpu_assemble(mesh, m, prec, scatter, kernel=nsa.KERNEL_GATHER, block_threads=nt)
+                if base is None:
+                    base = (v, r)
+                assert np.array_equal(v, base[0]) and np.array_equal(r, base[1]), (prec, tb, nt, scatter)

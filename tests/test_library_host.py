@@ -212,3 +212,80 @@ def test_tiling_arguments(lib):
     with pytest.raises(nsa.NsaError) as ei:
         mesh.tiles(nsa.COLOUR)
     assert ei.value.status == nsa.NSA_EUNSUPPORTED
+
+
+def check_gather_plan(m, mesh, lds_limit=160 * 1024):
+    """Every index the gather kernel derives from its plan stays inside its buffers, and the
+    contribution lists cover every (element, a, b) with an owned vertex a exactly once, in element
+    order, under the block the pattern maps it to."""
+    info = mesh.info
+    g = mesh.gather()
+    bptr, bcol, emap = mesh.pattern()
+    tr, tn, te, tp = g["tile_row"], g["tile_nptr"], g["tile_eptr"], g["tile_pptr"]
+    assert tr[0] == 0 and tr[-1] == m.npoin and np.all(np.diff(tr) > 0)
+    assert info.gather_pairs == 16 * m.nelem == tp[-1]
+    nnod, nrec, npr = np.diff(tn), np.diff(te), np.diff(tp)
+    lds64 = [((48 * n + 15) // 16 * 16) + r * (8 * 46 + 8) + (2 * q + 15) // 16 * 16 for n, r, q in zip(nnod, nrec, npr)]
+    lds32 = [((48 * n + 15) // 16 * 16) + r * (4 * 44 + 8) + (2 * q + 15) // 16 * 16 for n, r, q in zip(nnod, nrec, npr)]
+    assert info.gather_lds_bytes[0] == max(lds64) <= lds_limit
+    assert info.gather_lds_bytes[1] == max(lds32) <= 80 * 1024
+    assert nrec.max() <= 4095 and np.diff(tp).max() <= 65535
+    n2e = [[] for _ in range(m.npoin)]
+    for e, nodes in enumerate(m.lnods):
+        for a in nodes:
+            n2e[a].append(e)
+    seen = np.zeros((m.nelem, 4, 4), np.int64)
+    for k in range(len(tr) - 1):
+        r0, r1 = int(tr[k]), int(tr[k + 1])
+        nr = r1 - r0
+        b0, nb = int(bptr[r0]), int(bptr[r1] - bptr[r0])
+        assert nb <= max(info.gather_tile_blocks, int(bptr[r0 + 1] - bptr[r0]))
+        els = g["elems"][te[k]:te[k + 1]]
+        assert els.tolist() == sorted({e for i in range(r0, r1) for e in n2e[i]}), "records: ascending elements"
+        nodes = g["tile_nodes"][tn[k]:tn[k + 1]]
+        assert np.array_equal(nodes[:nr], np.arange(r0, r1))
+        assert np.all(np.diff(nodes[nr:]) > 0) and not np.any((nodes[nr:] >= r0) & (nodes[nr:] < r1))
+        loc = g["local_nodes"][te[k]:te[k + 1]].astype(np.int64)
+        assert loc.max() < nodes.size
+        assert np.array_equal(nodes[loc], m.lnods[els]), "local ids in the element's own vertex order"
+        slots = g["slots"][b0:b0 + nb]
+        blk = (slots >> 16).astype(np.int64)
+        beg = (slots & 0xFFFF).astype(np.int64)
+        assert np.array_equal(np.sort(blk), np.arange(nb)), "slots: a permutation of the tile's blocks"
+        npair = int(tp[k + 1] - tp[k])
+        end = np.append(beg[1:], npair)
+        assert beg[0] == 0 and np.all(end > beg), "every block has a non-empty list"
+        assert np.all(np.diff(end - beg) <= 0), "lists from long to short"
+        pairs = g["pairs"][tp[k]:tp[k + 1]].astype(np.int64)
+        for s in range(nb):
+            lst = pairs[beg[s]:end[s]]
+            rec, a, b = lst >> 4, (lst >> 2) & 3, lst & 3
+            assert np.all(rec < len(els)) and np.all(np.diff(rec) > 0), "one entry per element, ascending"
+            e = els[rec]
+            assert np.all(emap[e, a, b] == b0 + blk[s]), "entry lands on its block"
+            assert np.all((m.lnods[e, a] >= r0) & (m.lnods[e, a] < r1)), "row vertex owned by the tile"
+            seen[e, a, b] += 1
+    assert np.all(seen == 1), "every (element, a, b) exactly once"
+
+
+@pytest.mark.parametrize("tile_blocks", [64, 200, 512, 4096])
+def test_gather_plan_in_bounds(lib, tile_blocks):
+    m = inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=34)
+    mesh = nsa.Mesh(m.lnods, m.coord, tile_blocks_gather=tile_blocks)
+    assert mesh.info.gather_ntiles >= 1 and mesh.info.gather_tile_blocks == tile_blocks
+    check_gather_plan(m, mesh)
+
+
+def test_gather_plan_random_numbering_and_defaults(lib):
+    m = inputs.make_mesh(6, jitter=True, permute=True, seed=35)
+    assert nsa.Mesh.from_inputs(m).info.gather_ntiles == 0, "opt-in"
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=512)
+    assert mesh.info.gather_tile_blocks == 512 and mesh.info.gather_threads == 256
+    check_gather_plan(m, mesh)
+    m1 = inputs.make_mesh(1, seed=36)
+    check_gather_plan(m1, nsa.Mesh.from_inputs(m1, tile_blocks_gather=64))
+    # dropping the plan
+    mesh0 = nsa.Mesh.from_inputs(m, tile_blocks_gather=0)
+    assert mesh0.info.gather_ntiles == 0
+    with pytest.raises(nsa.NsaError):
+        mesh0.gather()
