@@ -266,6 +266,16 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
  * captured graph replays with whatever inputs the last nsa_batch_set_inputs installed. */
 nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream);
 
+/* ---- synthetic inputs ---------------------------------------------------------------------- */
+
+/* Seeded uniform values (a convenience for synthetic inputs such as request velocities; not part
+ * of the assembly): out[i] = lo + (hi - lo) * u_i for 0 <= i < n, with u_i = (z_i >> 11) * 2^-53 and
+ * z_i = splitmix64 of the counter seed + (i + 1) * 0x9E3779B97F4A7C15 (the mixing function of Steele,
+ * Lea and Flood: z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
+ * z ^= z >> 31); the product and the sum are rounded separately. out: device FP64, 8-byte aligned.
+ * Asynchronous on stream. Errors: NSA_EINVAL, NSA_EHIP. */
+nsa_status nsa_fill_uniform(double *out, int64_t n, uint64_t seed, double lo, double hi, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

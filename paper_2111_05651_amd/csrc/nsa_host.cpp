@@ -1389,5 +1389,14 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     return st ? st : ok();
 }
 
+
+nsa_status nsa_fill_uniform(double *out, int64_t n, uint64_t seed, double lo, double hi, void *stream) {
+    if (n < 0 || (n > 0 && !out)) return fail(NSA_EINVAL, "nsa_fill_uniform: bad arguments");
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi >= lo)) return fail(NSA_EINVAL, "need finite lo <= hi");
+    if (((uintptr_t)out) % 8) return fail(NSA_EINVAL, "out must be 8-byte aligned");
+    nsa_status st = hip_check(nsa::launch_fill_uniform(out, n, seed, lo, hi, (hipStream_t)stream), "fill uniform");
+    return st ? st : ok();
+}
+
 }  // extern "C"
 

@@ -38,6 +38,7 @@ struct AsmArgs {
 enum class Kern { AtomicF64, AtomicMixed, ColourF64, ColourMixed };
 
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_fill_uniform(double *p, int64_t n, uint64_t seed, double lo, double hi, hipStream_t s);
 hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s);
 
 // Row tiles: tile t owns the contiguous block rows [row[t], row[t+1]) and therefore the contiguous

@@ -222,6 +222,22 @@ __global__ void k_fill_zero_tail(double *p, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && (n & 1)) p[n - 1] = 0.0;
 }
 
+// Seeded uniform values for synthetic inputs: value i is lo + (hi - lo) u_i with u_i the top 53
+// bits of splitmix64 (Steele, Lea and Flood's mixing function) at counter seed + (i + 1) * gamma,
+// gamma = 2^64 / golden ratio. Multiply and add are rounded separately so that any other
+// implementation of the same definition gives the same bits.
+__global__ void k_fill_uniform(double *p, int64_t n, uint64_t seed, double lo, double span) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * 0x1.0p-53;
+        p[i] = __dadd_rn(lo, __dmul_rn(span, u));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
@@ -233,6 +249,13 @@ hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
                            reinterpret_cast<double2 *>(p), n2);
     }
     if (n & 1) hipLaunchKernelGGL(k_fill_zero_tail, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(double *p, int64_t n, uint64_t seed, double lo, double hi, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)blocks), dim3(256), 0, s, p, n, seed, lo, hi - lo);
     return hipGetLastError();
 }
 

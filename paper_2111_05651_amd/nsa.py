@@ -25,7 +25,7 @@ EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_co
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
-           "nsa_assemble_batched"]
+           "nsa_assemble_batched", "nsa_fill_uniform"]
 
 
 class NsaError(RuntimeError):
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_batch_upload.argtypes = [P, P, sz, P]
     lib.nsa_batch_set_inputs.argtypes = [P, P, P, P, P, P, P, i32, P]
     lib.nsa_assemble_batched.argtypes = [P, C.POINTER(Options), i32, P]
+    lib.nsa_fill_uniform.argtypes = [P, i64, C.c_uint64, d, d, P]
     for name in EXPORTS:
         if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
             getattr(lib, name).restype = i32
@@ -280,6 +281,16 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
     _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
                                _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
     return values, rhs
+
+
+def fill_uniform(out, seed: int, lo: float = -1.0, hi: float = 1.0, stream=None):
+    """Fill a contiguous float64 device tensor with the library's seeded uniform values."""
+    import torch
+    if not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.is_contiguous() and out.is_cuda):
+        raise ValueError("out must be a contiguous float64 device tensor")
+    _check(load().nsa_fill_uniform(out.data_ptr(), out.numel(), int(seed) % (1 << 64), float(lo), float(hi),
+                                   _stream_handle(stream)), "nsa_fill_uniform")
+    return out
 
 
 class Batch:

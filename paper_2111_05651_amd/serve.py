@@ -2,7 +2,7 @@
 
 A Server keeps a set of meshes resident on the device (tile plans, block pattern and coordinates
 uploaded once) and accepts assembly requests from any thread: a mesh id, the advection velocity (a
-device tensor, or a seed from which the server draws U[-1,1]^3 per node on the device), rho, mu and
+device tensor, or a seed from which the server draws U[-1,1)^3 per node on the device), rho, mu and
 dt. One scheduler loop moves each request through
 
   queued -> admitted -> running -> done            (or rejected / timeout / failed)
@@ -511,7 +511,6 @@ class GpuExecutor:
                 raise ServerError(f"mesh {i} is not uploaded with a tile plan for scatter mode {self.scatter}")
         self.resident_bytes = sum(int(h.ws.numel()) for h in self.meshes) + \
             sum(int(b.ws.numel()) for b in self.batches)
-        self._gen = torch.Generator(device=self.device)
         self._arena = None
         # trace: device-clock interval of every launch's kernel, in ms from a reference event
         self.trace = trace
@@ -554,13 +553,13 @@ class GpuExecutor:
                              f"{self.device}")
 
     def velocity(self, i, seed, out=None):
-        """The velocity a request with this seed uses: U[-1,1]^3 per node, drawn on the device."""
+        """The velocity a request with this seed uses: U[-1,1)^3 per node, drawn on the device by the
+        library's seeded generator (nsa_fill_uniform) on the current stream."""
         import torch
         m = self.meshes[i]
-        self._gen.manual_seed(int(seed))
         if out is None:
             out = torch.empty((m.npoin, 3), dtype=torch.float64, device=self.device)
-        return out.uniform_(-1.0, 1.0, generator=self._gen)
+        return nsa.fill_uniform(out, seed, -1.0, 1.0, torch.cuda.current_stream(self.device))
 
     # launches
     def launch(self, slot, reqs):

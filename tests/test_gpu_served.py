@@ -157,3 +157,29 @@ def test_served_caller_velocity_and_concurrent_clients(meshes):
     for i, r in got[0] + got[1]:
         assert torch.equal(r.values, plain[i][0]) and torch.equal(r.rhs, plain[i][1])
         r.release()
+
+
+def splitmix_uniform(n, seed, lo, hi):
+    """lo + (hi - lo) * u_i, u_i = top 53 bits of splitmix64 at counter seed + (i + 1) * gamma,
+    written from the generator's published definition (independent of the library's kernel)."""
+    i = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed % (1 << 64)) + i * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return lo + (hi - lo) * u
+
+
+@pytest.mark.parametrize("n,seed,lo,hi", [(0, 5, 0.0, 1.0), (1, 0, -1.0, 1.0), (777, 2 ** 64 - 1, 0.5, 2.0),
+                                          (3 * 274625, 123456789, -1.0, 1.0)])
+def test_fill_uniform_matches_definition(n, seed, lo, hi):
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    nsa.fill_uniform(out, seed, lo, hi)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.array_equal(got, splitmix_uniform(n, seed, lo, hi)), "bitwise equal to the definition"
+    if n > 100000:
+        assert got.min() >= lo and got.max() < hi and abs(got.mean() - 0.5 * (lo + hi)) < 5e-3
+        assert np.unique(got).size == n

@@ -289,3 +289,12 @@ def test_gather_plan_random_numbering_and_defaults(lib):
     assert mesh0.info.gather_ntiles == 0
     with pytest.raises(nsa.NsaError):
         mesh0.gather()
+
+
+def test_fill_uniform_argument_checks(lib):
+    """Rejected before anything is launched (no device needed)."""
+    assert lib.nsa_fill_uniform(None, -1, 0, 0.0, 1.0, None) == nsa.NSA_EINVAL
+    assert lib.nsa_fill_uniform(None, 5, 0, 0.0, 1.0, None) == nsa.NSA_EINVAL
+    assert lib.nsa_fill_uniform(8, 5, 0, 1.0, 0.0, None) == nsa.NSA_EINVAL
+    assert lib.nsa_fill_uniform(8, 5, 0, float("nan"), 1.0, None) == nsa.NSA_EINVAL
+    assert lib.nsa_fill_uniform(12, 5, 0, 0.0, 1.0, None) == nsa.NSA_EINVAL  # misaligned
