@@ -7,7 +7,7 @@ The arithmetic lives in ``nsa_oracle.c`` (plain C, built with ``-O2 -ffp-contrac
 this module only compiles it and marshals NumPy arrays through ctypes.
 """
 from .oracle import (build, load, element, element_integrals, validate, pattern, assemble,
-                     assemble_rows, OR_OK, OR_EINVAL, OR_ERANGE, OR_EDEGENERATE, OR_ENOMEM)
+                     assemble_rows, residual, OR_OK, OR_EINVAL, OR_ERANGE, OR_EDEGENERATE, OR_ENOMEM)
 
 __all__ = ["build", "load", "element", "element_integrals", "validate", "pattern", "assemble",
-           "assemble_rows", "OR_OK", "OR_EINVAL", "OR_ERANGE", "OR_EDEGENERATE", "OR_ENOMEM"]
+           "assemble_rows", "residual", "OR_OK", "OR_EINVAL", "OR_ERANGE", "OR_EDEGENERATE", "OR_ENOMEM"]

@@ -396,6 +396,46 @@ int oracle_assemble(int64_t npoin, int64_t nelem, const int32_t *lnods, const do
     return OR_OK;
 }
 
+/* Explicit-residual assembly: the outputs of Listing 2 (rhsid, dt_rho_nsi, mass_rho_nsi) instead
+ * of a matrix. Per element, after the pipeline of Listing 1:
+ *   elrbu(c, a)  = elrhs[4a+c] - sum_b sum_c' elauu[4a+c][4b+c'] * elvel[b][c']   (c, c' < 3)
+ *                  (the momentum residual of the element with the nodal velocities as the trial
+ *                  field; the pressure is not an input of Listing 2 and enters as zero);
+ *   eldtrho(a)   = sum_g gpvol[g] * shape[g][a] * tau1   (tau-weighted lumped mass), and
+ *   elmurho(a)   = sum_g gpvol[g] * shape[g][a] * rho    (rho-weighted lumped mass),
+ * the two per-node quantities calculate_tau_and_tim hands to the scatter (a reading: the paper does
+ * not define them). rhsid [npoin][3], dt_rho [npoin] and mass_rho [npoin] are zeroed, then every
+ * element adds into the rows of its nodes through lnods, elements in ascending order. */
+int oracle_residual(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
+                    const double *veloc, double rho, double mu, double dt, double *rhsid,
+                    double *dt_rho, double *mass_rho)
+{
+    memset(rhsid, 0, sizeof(double) * 3 * (size_t)npoin);
+    memset(dt_rho, 0, sizeof(double) * (size_t)npoin);
+    memset(mass_rho, 0, sizeof(double) * (size_t)npoin);
+    for (int64_t e = 0; e < nelem; e++) {
+        element_t E;
+        double X[PNODE][NDIME], U[PNODE][NDIME];
+        calculate_transients(lnods + 4 * e, coord, veloc, X, U);
+        int st = element_pipeline(X, U, rho, mu, dt, &E);
+        if (st != OR_OK) return st;
+        for (int a = 0; a < PNODE; a++) {
+            int64_t ipoin = lnods[4 * e + a];
+            for (int c = 0; c < NDIME; c++) {
+                double r = E.elrhs[4 * a + c];
+                for (int b = 0; b < PNODE; b++)
+                    for (int cp = 0; cp < NDIME; cp++) r -= E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];
+                rhsid[3 * ipoin + c] += r;
+            }
+            double lump = 0.0;
+            for (int g = 0; g < PGAUS; g++) lump += E.gpvol[g] * E.shape[g][a];
+            dt_rho[ipoin] += lump * E.tau1;
+            mass_rho[ipoin] += lump * rho;
+        }
+    }
+    return OR_OK;
+}
+
 /* Assembly restricted to a sample of rows, for checking large meshes one row at a time.
  * rowslot[i] is the position of node i in the sample (or -1). For sampled row s, its pattern
  * is rebuilt from the elements that touch it: cols[s*maxdeg + k] (ascending, -1 padded),

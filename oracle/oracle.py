@@ -40,6 +40,8 @@ def _bind(lib):
     lib.oracle_assemble.restype = C.c_int
     lib.oracle_assemble_rows.argtypes = [i64, i64, P, P, P, d, d, d, i64, P, i32, P, P, P, P]
     lib.oracle_assemble_rows.restype = C.c_int
+    lib.oracle_residual.argtypes = [i64, i64, P, P, P, d, d, d, P, P, P]
+    lib.oracle_residual.restype = C.c_int
     return lib
 
 
@@ -137,6 +139,24 @@ def assemble(mesh, pat=None, lib=None, rho=None, mu=None, dt=None, velocity=None
     if st != OR_OK:
         raise ValueError(f"oracle_assemble status {st}")
     return values, rhs
+
+
+def residual(mesh, lib=None, rho=None, mu=None, dt=None, velocity=None):
+    """Explicit-residual outputs of Listing 2 for a Mesh: (rhsid [npoin][3], dt_rho [npoin],
+    mass_rho [npoin])."""
+    lib = lib or load()
+    ln = np.ascontiguousarray(mesh.lnods, dtype=np.int32)
+    co = _f64(mesh.coord)
+    ve = _f64(mesh.velocity if velocity is None else velocity)
+    rhsid = np.zeros((mesh.npoin, 3))
+    dt_rho = np.zeros(mesh.npoin)
+    mass_rho = np.zeros(mesh.npoin)
+    st = lib.oracle_residual(mesh.npoin, mesh.nelem, _p(ln), _p(co), _p(ve),
+                             mesh.rho if rho is None else rho, mesh.mu if mu is None else mu,
+                             mesh.dt if dt is None else dt, _p(rhsid), _p(dt_rho), _p(mass_rho))
+    if st != OR_OK:
+        raise ValueError(f"oracle_residual status {st}")
+    return rhsid, dt_rho, mass_rho
 
 
 def assemble_rows(mesh, rows, maxdeg=64, lib=None, velocity=None, rho=None, mu=None, dt=None):

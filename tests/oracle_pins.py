@@ -420,6 +420,54 @@ def pin_renumbering(lib, n=3, seed=22):
     _close(r2[perm], r0, 0, 1e-12 * np.abs(r0).max(), "renumbering invariance of the RHS")
 
 
+def pin_residual_uniform_flow(lib, n=3, seed=23):
+    """Explicit residual: a uniform velocity field leaves no residual at any node. With U_b = u for
+    every node, sum_b grad N_b = 0 removes the convective, viscous, grad-div and SUPG-convective
+    parts of A_uu u, and what is left, (rho/dt) V/4 u + tau1 rho (rho/dt) V (u . grad N_a) u, is the
+    element RHS term by term."""
+    m = inputs.make_mesh(n, jitter=True, permute=True, seed=seed, rho=1.3, mu=2e-3, dt=4e-3)
+    for ubar in (np.array([0.7, -0.4, 0.25]), np.array([0.0, 0.0, 2.0])):
+        U = np.tile(ubar, (m.npoin, 1))
+        rhsid, _, _ = oracle.residual(m, lib=lib, velocity=U)
+        _, rhs = oracle.assemble(m, lib=lib, velocity=U)
+        _close(rhsid, np.zeros_like(rhsid), 0, 1e-12 * np.abs(rhs[:, :3]).max(), "uniform-flow residual")
+
+
+def pin_residual_csr_route(lib, n=3, seed=24):
+    """Explicit residual against a second route: the assembled block-CSR matrix applied to the
+    nodal velocities (pressure zero), subtracted from the assembled RHS."""
+    m = inputs.make_mesh(n, jitter=True, permute=True, velocity="uniform", seed=seed)
+    pat = oracle.pattern(m.npoin, m.lnods, lib=lib)
+    values, rhs = oracle.assemble(m, pat, lib=lib)
+    bptr, bcol, _ = pat
+    rows = np.repeat(np.arange(m.npoin), np.diff(bptr))
+    av = np.zeros((m.npoin, 3))
+    np.add.at(av, rows, np.einsum("kij,kj->ki", values[:, :3, :3], m.velocity[bcol]))
+    want = rhs[:, :3] - av
+    rhsid, _, _ = oracle.residual(m, lib=lib)
+    _close(rhsid, want, 0, 1e-12 * np.abs(want).max(), "residual vs rhs - A u")
+
+
+def pin_residual_lumped(lib, n=3, seed=25):
+    """Lumped masses: mass_rho at node i is rho sum_{e ni i} V_e / 4 with V_e = |det| / 6 from NumPy;
+    their total is rho times the mesh volume; dt_rho at node i is sum_{e ni i} tau1_e V_e / 4 with
+    tau1_e and V_e of the (pinned) element routine."""
+    m = inputs.make_mesh(n, jitter=True, permute=True, velocity="vortex", seed=seed, rho=0.8, mu=5e-3, dt=2e-3)
+    _, dt_rho, mass_rho = oracle.residual(m, lib=lib)
+    X = m.coord[m.lnods]
+    vol = np.abs(np.linalg.det(X[:, 1:, :] - X[:, :1, :])) / 6.0
+    want = np.zeros(m.npoin)
+    np.add.at(want, m.lnods.ravel(), np.repeat(m.rho * vol / 4.0, 4))
+    _close(mass_rho, want, 0, 1e-14 * want.max(), "rho-weighted lumped mass")
+    _close(np.array([mass_rho.sum()]), np.array([m.rho * vol.sum()]), 0, 1e-13, "total rho-weighted mass")
+    w = np.zeros(m.npoin)
+    for e in range(m.nelem):
+        it = oracle.element_integrals(m.coord[m.lnods[e]], m.velocity[m.lnods[e]], m.rho, m.mu, m.dt, lib=lib)
+        w[m.lnods[e]] += it["tau1"] * it["V"] / 4.0
+    _close(dt_rho, w, 0, 1e-14 * w.max(), "tau-weighted lumped mass")
+
+
 ALL_PINS = [pin_golden, pin_geometry, pin_integrals_exact, pin_integrals_gm, pin_element_invariants,
             pin_viscous_kernel, pin_rotation_translation, pin_pattern, pin_kuhn_stencil,
-            pin_divergence_theorem, pin_renumbering]
+            pin_divergence_theorem, pin_renumbering, pin_residual_uniform_flow, pin_residual_csr_route,
+            pin_residual_lumped]

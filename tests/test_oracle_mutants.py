@@ -50,6 +50,12 @@ MUTANTS = {
     "rhs_wrong_node": ("double *r = rhs + 4 * (size_t)lnods[4 * e + a];", "double *r = rhs + 4 * (size_t)lnods[4 * e + (a + 1) % 4];"),
     "pattern_keeps_duplicates": ("if (k == lo || pairs[k] != pairs[k - 1]) bcol[nnzb++] = pairs[k];", "bcol[nnzb++] = pairs[k];"),
     "emap_search_off": ("if (bcol[mid] < col) lo = mid + 1; else hi = mid;", "if (bcol[mid] <= col) lo = mid + 1; else hi = mid;"),
+    "residual_sign": ("r -= E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];", "r += E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];"),
+    "residual_transposed": ("r -= E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];", "r -= E.elauu[4 * b + cp][4 * a + c] * E.elvel[b][cp];"),
+    "residual_with_pressure_column": ("for (int cp = 0; cp < NDIME; cp++) r -=", "for (int cp = 0; cp < NDOFN; cp++) r -="),
+    "residual_wrong_velocity_node": ("E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];", "E.elauu[4 * a + c][4 * b + cp] * E.elvel[a][cp];"),
+    "lumped_tau2": ("dt_rho[ipoin] += lump * E.tau1;", "dt_rho[ipoin] += lump * E.tau2;"),
+    "lumped_no_shape": ("lump += E.gpvol[g] * E.shape[g][a];", "lump += E.gpvol[g];"),
 }
 
 DRIVER = r"""
