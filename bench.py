@@ -100,6 +100,100 @@ def cpu_baseline(m, nelem_sample):
                       f"(pattern build untimed), {dt:.1f} s"}
 
 
+def cpu_baseline_residual(m):
+    """The oracle's explicit-residual routine (serial C, FP64) on the whole mesh."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.residual(m)
+    dt = time.perf_counter() - t0
+    return {"value": m.nelem / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {m.nelem} elements of the same mesh, serial FP64 C oracle (residual outputs), "
+                      f"{dt:.1f} s"}
+
+
+FLOPS_FILE = os.path.join(ROOT, "profiles", "residual_flops.json")
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector
+PEAK_FP32_TFLOPS = 78.6        # FP32 vector without packed instructions (the build disables them)
+
+
+def residual_flops(kernel_key):
+    """VALU flops per element (FP64, FP32) of the residual kernel from the committed counter
+    summary, if it was taken on this kernel source."""
+    try:
+        with open(FLOPS_FILE) as f:
+            rec = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != source_digest():
+        return None
+    return rec
+
+
+def run_residual(args, m, prec):
+    """The explicit-residual outputs of Listing 2 (rhsid, dt_rho_nsi, mass_rho_nsi), no matrix."""
+    import torch
+    from paper_2111_05651_amd import nsa
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=0, tile_blocks_colour=0, tile_rows_residual=args.tile_rows_residual,
+                                keep_direct=False)
+    mesh.upload("cuda:0")
+    info = mesh.info
+    log(f"mesh registered: residual tiles={info.residual_ntiles} records/nelem="
+        f"{info.residual_records / max(m.nelem, 1):.2f} lds={info.residual_lds_bytes}")
+    vel = torch.from_numpy(m.velocity).to("cuda:0")
+    r = torch.empty((m.npoin, 3), dtype=torch.float64, device="cuda:0")
+    t = torch.empty(m.npoin, dtype=torch.float64, device="cuda:0")
+    w = torch.empty_like(t)
+    stream = torch.cuda.current_stream()
+
+    def step(p=prec):
+        nsa.assemble_residual(mesh, vel, m.rho, m.mu, m.dt, precision=p, rhsid=r, dt_rho=t, mass_rho=w, stream=stream)
+
+    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
+    beside = None
+    if not args.no_beside:
+        other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED
+        first = [x.clone() for x in (r, t, w)]
+        ms_o, _, _ = time_steps(lambda: step(other), args.steps, args.warmup, stream)
+        f64, mix = (first, (r, t, w)) if other == nsa.MIXED else ((r, t, w), first)
+        err = {n: float((a - b).abs().max() / b.abs().max()) for n, a, b in zip(("rhsid", "dt_rho", "mass_rho"), mix, f64)}
+        beside = {"precision": "mixed" if other == nsa.MIXED else "fp64", "value": m.nelem / (ms_o / 1e3),
+                  "ms_per_step": ms_o, "unit": "elements/s", "same_gpu": True, "mixed_vs_fp64_error": err}
+        log(f"{beside['precision']} beside it: {ms_o:.4f} ms/step; mixed vs FP64 errors {err}")
+    launch_ms = statistics.fmean(per)
+    rt = "float" if prec == nsa.MIXED else "double"
+    kname = f"k_residual<{rt},256>"
+    fl = residual_flops(f"{kname}@{args.workload}/rows{args.tile_rows_residual}")
+    if fl:
+        flops = (fl["fp64_flops_per_element"] + fl["fp32_flops_per_element"]) * m.nelem
+        peak = PEAK_FP64_TFLOPS if prec == nsa.FP64 else PEAK_FP32_TFLOPS
+        achieved = flops / (launch_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": kname, "flops_per_element": flops / m.nelem,
+                "flops_basis": "VALU flops per element counted by rocprofv3 on this kernel",
+                "avg_launch_ms": launch_ms}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": kname, "avg_launch_ms": launch_ms,
+                "note": "no counter-measured flop count for this kernel source"}
+    nbytes = 16 * m.nelem + 48 * m.npoin + 40 * m.npoin
+    line = {
+        "metric": "elements assembled/s (explicit-residual outputs)", "value": m.nelem / (ms / 1e3),
+        "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == nsa.MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {m.name}", "path": "residual", "nelem": m.nelem, "npoin": m.npoin,
+                   "precision": args.precision, "rows_per_tile": args.tile_rows_residual, "rho": m.rho, "mu": m.mu,
+                   "dt": m.dt},
+        "hbm_GBs": nbytes / (launch_ms / 1e3) / 1e9, "algorithmic_bytes_per_launch": nbytes,
+        "roofline": roof, "beside": beside,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle residual on the whole mesh ...")
+        line["cpu_baseline"] = cpu_baseline_residual(m)
+    print(json.dumps(line), flush=True)
+
+
 def traffic_for(kernel_key, launches_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on this
     exact kernel source and configuration; else None."""
@@ -323,6 +417,9 @@ def main():
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
     ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto", "gather"])
     ap.add_argument("--tile-blocks-gather", type=int, default=512, help="blocks per tile of the gather plan")
+    ap.add_argument("--path", default="matrix", choices=["matrix", "residual"],
+                    help="matrix: block-CSR values + RHS; residual: the explicit-residual outputs (no matrix)")
+    ap.add_argument("--tile-rows-residual", type=int, default=256, help="rows per tile of the residual plan")
     ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
     ap.add_argument("--tile-blocks-colour", type=int, default=256, help="tile size of the colour-mode plan")
@@ -372,6 +469,8 @@ def main():
     t0 = time.perf_counter()
     m = make_workload(args.workload)
     log(f"workload {args.workload}: {m.nelem} tets, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
+    if args.path == "residual":
+        return run_residual(args, m, prec)
     gather = kern == nsa.KERNEL_GATHER
     mesh = nsa.Mesh.from_inputs(m, tile_blocks=0 if gather else args.tile_blocks,
                                 tile_blocks_colour=0 if gather else args.tile_blocks_colour,

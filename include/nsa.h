@@ -75,8 +75,9 @@ typedef int32_t nsa_status;
                                   precomputed list of element contributions (element order) and
                                   stored once; no atomics, bit-reproducible in either scatter mode */
 
-/* plan index of nsa_mesh_set_tiling beside the two scatter modes */
+/* plan indices of nsa_mesh_set_tiling beside the two scatter modes */
 #define NSA_GATHER_PLAN 2
+#define NSA_RESIDUAL_PLAN 3
 
 typedef struct nsa_options {
     int32_t precision;         /* NSA_FP64 or NSA_MIXED */
@@ -110,6 +111,11 @@ typedef struct nsa_mesh_info {
     int32_t gather_tile_blocks;/* requested blocks per tile */
     int32_t gather_threads;    /* workgroup size */
     int32_t gather_lds_bytes[2]; /* LDS of the largest tile, [0] FP64, [1] mixed precision */
+    /* residual plan (nsa_assemble_residual) */
+    int64_t residual_ntiles;   /* 0 if there is none */
+    int64_t residual_records;  /* sum over tiles of the elements each tile evaluates */
+    int32_t residual_tile_rows;/* requested rows per tile */
+    int32_t residual_lds_bytes;/* LDS of the largest tile */
 } nsa_mesh_info;
 
 typedef struct nsa_mesh nsa_mesh; /* opaque */
@@ -164,7 +170,10 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
  * elements and 65535 element
  * contributions, whose LDS (48 bytes per touched node, 376 per element with FP64 element data,
  * 184 in mixed precision, 2 per contribution) stays within 80 KB in mixed precision and 160 KB in
- * FP64. */
+ * FP64.
+ * With scatter = NSA_RESIDUAL_PLAN it sizes the plan of nsa_assemble_residual, also built only when
+ * asked for: contiguous row ranges of at most tile_blocks rows (1..4096; 0 drops the plan) whose LDS
+ * (48 bytes per touched node, 40 per row) stays within 64 KB. */
 /* Whether nsa_mesh_upload also stores the direct kernel's arrays (SoA connectivity, element-to-block
  * map and their colour-ordered copies, ~160 bytes per element; default 1). With 0 the mesh can only
  * be assembled by the tiled kernel (NSA_KERNEL_DIRECT returns NSA_EUNSUPPORTED). Before upload. */
@@ -265,6 +274,29 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
  * No allocation, no memset, no host synchronisation: the call may be captured in a HIP graph, and a
  * captured graph replays with whatever inputs the last nsa_batch_set_inputs installed. */
 nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream);
+
+/* ---- explicit residual ---------------------------------------------------------------------- */
+
+/* Residual tiles (sizes from nsa_mesh_get_info; any array may be NULL): tile_row int32 [ntiles+1]
+ * (tile t owns rows tile_row[t] .. tile_row[t+1]-1), tile_eptr int64 [ntiles+1], elems int32
+ * [residual_records], local_nodes uint16 [residual_records][4] (owned nodes first), tile_nptr int64
+ * [ntiles+1], tile_nodes int32 (owned rows first, then the other touched nodes ascending). */
+nsa_status nsa_mesh_get_residual_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems,
+                                       uint16_t *local_nodes, int64_t *tile_nptr, int32_t *tile_nodes);
+/* The outputs of Listing 2's perform_assembly_in_global_system instead of a matrix: for every node
+ * i (sums over the elements that contain it, a = the vertex of the element at i)
+ *   rhsid[i][c]  += b_a[c] - sum_b sum_c' A_uu(a c, b c') U_b[c']    (c, c' = 0..2; the momentum
+ *                  residual of the element with the nodal velocities as the trial field and zero
+ *                  pressure; b and A are the RHS and the element matrix of nsa_assemble),
+ *   dt_rho[i]    += tau1 V / 4   and   mass_rho[i] += rho V / 4   (the tau- and rho-weighted
+ *                  lumped masses that calculate_tau_and_tim passes to the scatter: a reading, the
+ *                  paper does not define them).
+ * rhsid device FP64 [npoin][3], dt_rho and mass_rho device FP64 [npoin], 8-byte aligned; overwritten
+ * unless opt->accumulate. opt->scatter must be NSA_ATOMIC; the mesh needs a residual plan.
+ * Asynchronous on stream. Errors: NSA_EINVAL, NSA_ESTATE, NSA_EUNSUPPORTED, NSA_EHIP. */
+nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
+                                 const nsa_options *opt, double *rhsid, double *dt_rho, double *mass_rho,
+                                 void *stream);
 
 /* ---- synthetic inputs ---------------------------------------------------------------------- */
 

@@ -532,6 +532,115 @@ nsa_status build_gather(nsa_mesh *m, nsa::GatherPlan &P, int32_t tile_blocks, in
     return NSA_OK;
 }
 
+// Residual tiles (see nsa_internal.h): contiguous row ranges of at most tile_rows rows whose LDS
+// (48 bytes per touched node, 40 per owned row) stays within kResLds (two workgroups per CU or
+// more). Records: the elements touching the tile, local node ids owned nodes first, ordered by
+// owned-node count (descending) then element id, so that the lanes of a wavefront run the same
+// number of row iterations.
+constexpr int64_t kResLds = 64 * 1024;
+constexpr int32_t kMaxResRows = 4096;
+
+nsa_status build_rtiles(nsa_mesh *m, nsa::ResPlan &P, int32_t tile_rows) {
+    P = nsa::ResPlan();
+    P.tile_rows = tile_rows;
+    const int64_t np = m->npoin;
+    if (np == 0) return NSA_OK;
+    if (nsa::res_lds_bytes((int32_t)m->max_row_blocks, 1) > kResLds) return NSA_OK;
+    std::vector<int32_t> stamp(np, -1);
+    P.row.push_back(0);
+    int32_t tid = 0;
+    for (int64_t r0 = 0; r0 < np; tid++) {
+        int64_t r1 = r0, nodes = 0;
+        while (r1 < np) {
+            int64_t add = 0;
+            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) add += stamp[m->bcol[k]] != tid;
+            const int64_t need = nsa::res_lds_bytes((int32_t)(nodes + add), (int32_t)(r1 + 1 - r0));
+            if (r1 > r0 && (need > kResLds || r1 + 1 - r0 > tile_rows || nodes + add > 65535)) break;
+            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
+            nodes += add;
+            r1++;
+        }
+        P.row.push_back((int32_t)r1);
+        P.lds = std::max<int64_t>(P.lds, nsa::res_lds_bytes((int32_t)nodes, (int32_t)(r1 - r0)));
+        r0 = r1;
+    }
+    std::vector<int32_t>().swap(stamp);
+    const int64_t nt = (int64_t)P.row.size() - 1;
+    std::vector<int64_t> n2e_ptr;
+    std::vector<int32_t> n2e;
+    node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
+    struct Out {
+        std::vector<int32_t> els, nodes;
+        std::vector<uint2> recs;
+        std::vector<int64_t> cnt, ncnt;
+    };
+    std::vector<Out> outs(host_threads());
+    int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
+        Out &o = outs[ci];
+        std::vector<int32_t> els, other, nown, idx;
+        for (int64_t t = tb; t < te; t++) {
+            const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
+            els.clear();
+            for (int32_t i = r0; i < r1; i++) els.insert(els.end(), n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
+            std::sort(els.begin(), els.end());
+            els.erase(std::unique(els.begin(), els.end()), els.end());
+            other.clear();
+            for (int32_t e : els)
+                for (int a = 0; a < 4; a++) {
+                    const int32_t g = m->lnods[4 * (int64_t)e + a];
+                    if (g < r0 || g >= r1) other.push_back(g);
+                }
+            std::sort(other.begin(), other.end());
+            other.erase(std::unique(other.begin(), other.end()), other.end());
+            for (int32_t i = r0; i < r1; i++) o.nodes.push_back(i);
+            o.nodes.insert(o.nodes.end(), other.begin(), other.end());
+            o.ncnt.push_back((int64_t)nr + (int64_t)other.size());
+            auto local = [&](int32_t g) -> uint32_t {
+                if (g >= r0 && g < r1) return (uint32_t)(g - r0);
+                return (uint32_t)(nr + (std::lower_bound(other.begin(), other.end(), g) - other.begin()));
+            };
+            const size_t ne = els.size();
+            nown.assign(ne, 0);
+            for (size_t j = 0; j < ne; j++)
+                for (int a = 0; a < 4; a++) {
+                    const int32_t g = m->lnods[4 * (int64_t)els[j] + a];
+                    nown[j] += g >= r0 && g < r1;
+                }
+            idx.resize(ne);
+            for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
+            std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return nown[x] > nown[y]; });
+            for (int32_t j : idx) {
+                const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
+                uint32_t l[4];
+                int k = 0;
+                for (int a = 0; a < 4; a++)
+                    if (ln[a] >= r0 && ln[a] < r1) l[k++] = local(ln[a]);
+                for (int a = 0; a < 4; a++)
+                    if (!(ln[a] >= r0 && ln[a] < r1)) l[k++] = local(ln[a]);
+                o.recs.push_back(make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16));
+                o.els.push_back(els[j]);
+            }
+            o.cnt.push_back((int64_t)ne);
+        }
+    });
+    P.eptr.assign(1, 0);
+    P.nptr.assign(1, 0);
+    for (int i = 0; i < used; i++) {
+        Out &o = outs[i];
+        for (size_t k = 0; k < o.cnt.size(); k++) {
+            P.eptr.push_back(P.eptr.back() + o.cnt[k]);
+            P.nptr.push_back(P.nptr.back() + o.ncnt[k]);
+        }
+        P.elems.insert(P.elems.end(), o.els.begin(), o.els.end());
+        P.nodes.insert(P.nodes.end(), o.nodes.begin(), o.nodes.end());
+        P.recs.insert(P.recs.end(), o.recs.begin(), o.recs.end());
+        o = Out();
+    }
+    if ((int64_t)P.eptr.size() != nt + 1) return fail(NSA_EUNSUPPORTED, "residual plan inconsistent");
+    P.ok = true;
+    return NSA_OK;
+}
+
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 void plan_layout(nsa_mesh *m) {
@@ -548,7 +657,7 @@ void plan_layout(nsa_mesh *m) {
     take(m->r_emap, d ? 16 * ne * sizeof(int32_t) : 0);
     take(m->r_ln_c, d ? 4 * ne * sizeof(int32_t) : 0);
     take(m->r_emap_c, d ? 16 * ne * sizeof(int32_t) : 0);
-    const bool t = m->plan[0].ok || m->plan[1].ok || m->gplan.ok;
+    const bool t = m->plan[0].ok || m->plan[1].ok || m->gplan.ok || m->rplan.ok;
     take(m->r_coord4, t ? 4 * np * sizeof(double) : 0);
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
     for (nsa::TilePlan &P : m->plan) {
@@ -567,6 +676,12 @@ void plan_layout(nsa_mesh *m) {
     take(G.r_pptr, G.ok ? G.pptr.size() * sizeof(int64_t) : 0);
     take(G.r_pairs, G.ok ? G.pairs.size() * sizeof(uint16_t) : 0);
     take(G.r_slots, G.ok ? G.slots.size() * sizeof(uint32_t) : 0);
+    nsa::ResPlan &RP = m->rplan;
+    take(RP.r_row, RP.ok ? RP.row.size() * sizeof(int32_t) : 0);
+    take(RP.r_eptr, RP.ok ? RP.eptr.size() * sizeof(int64_t) : 0);
+    take(RP.r_nptr, RP.ok ? RP.nptr.size() * sizeof(int64_t) : 0);
+    take(RP.r_nodes, RP.ok ? RP.nodes.size() * sizeof(int32_t) : 0);
+    take(RP.r_recs, RP.ok ? RP.recs.size() * sizeof(uint2) : 0);
     m->ws_bytes = std::max<size_t>(off, 256);
 }
 
@@ -590,6 +705,12 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
             if (st) return st;
         } else {
             m->gplan = nsa::GatherPlan();
+        }
+        if (m->want_res > 0) {
+            nsa_status st = build_rtiles(m, m->rplan, m->want_res);
+            if (st) return st;
+        } else {
+            m->rplan = nsa::ResPlan();
         }
         plan_layout(m);
     } catch (const std::bad_alloc &) {
@@ -732,13 +853,25 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
 
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_set_tiling: null mesh");
-    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR && scatter != NSA_GATHER_PLAN)
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR && scatter != NSA_GATHER_PLAN && scatter != NSA_RESIDUAL_PLAN)
         return fail(NSA_EINVAL, "unknown plan %d", scatter);
-    const int32_t cap = scatter == NSA_GATHER_PLAN ? kMaxGatherBlocks : kMaxTileBlocks;
-    if (tile_blocks != 0 && (tile_blocks < 64 || tile_blocks > cap))
-        return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d] (or 0)", tile_blocks, cap);
+    if (scatter == NSA_RESIDUAL_PLAN) {
+        if (tile_blocks != 0 && (tile_blocks < 1 || tile_blocks > kMaxResRows))
+            return fail(NSA_EINVAL, "rows per residual tile %d outside [1, %d] (or 0)", tile_blocks, kMaxResRows);
+    } else {
+        const int32_t cap = scatter == NSA_GATHER_PLAN ? kMaxGatherBlocks : kMaxTileBlocks;
+        if (tile_blocks != 0 && (tile_blocks < 64 || tile_blocks > cap))
+            return fail(NSA_EINVAL, "tile_blocks %d outside [64, %d] (or 0)", tile_blocks, cap);
+    }
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tiling after upload");
     std::lock_guard<std::mutex> g(m->plan_mu);
+    if (scatter == NSA_RESIDUAL_PLAN) {
+        if (m->want_res != tile_blocks || !m->planned) {
+            m->want_res = tile_blocks;
+            m->planned = false;
+        }
+        return ok();
+    }
     if (scatter == NSA_GATHER_PLAN) {
         if (m->want_gather != tile_blocks || !m->planned) {
             m->want_gather = tile_blocks;
@@ -799,6 +932,11 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
     info->gather_threads = G.threads;
     info->gather_lds_bytes[0] = G.ok ? (int32_t)G.lds[0] : 0;
     info->gather_lds_bytes[1] = G.ok ? (int32_t)G.lds[1] : 0;
+    const nsa::ResPlan &RP = m->rplan;
+    info->residual_ntiles = RP.ntiles();
+    info->residual_records = RP.ok ? RP.eptr.back() : 0;
+    info->residual_tile_rows = RP.tile_rows;
+    info->residual_lds_bytes = RP.ok ? (int32_t)RP.lds : 0;
     return ok();
 }
 
@@ -860,6 +998,23 @@ nsa_status nsa_mesh_get_gather(const nsa_mesh *m, int32_t *tile_row, int64_t *ti
     return ok();
 }
 
+nsa_status nsa_mesh_get_residual_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems,
+                                       uint16_t *local_nodes, int64_t *tile_nptr, int32_t *tile_nodes) {
+    if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_residual_tiles: null mesh");
+    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    nsa_status st = ensure_plans(m);
+    if (st) return st;
+    const nsa::ResPlan &RP = m->rplan;
+    if (!RP.ok) return fail(NSA_EUNSUPPORTED, "no residual plan for this mesh");
+    if (tile_row) std::copy(RP.row.begin(), RP.row.end(), tile_row);
+    if (tile_eptr) std::copy(RP.eptr.begin(), RP.eptr.end(), tile_eptr);
+    if (elems) std::copy(RP.elems.begin(), RP.elems.end(), elems);
+    if (local_nodes) std::memcpy(local_nodes, RP.recs.data(), RP.recs.size() * sizeof(uint2));
+    if (tile_nptr) std::copy(RP.nptr.begin(), RP.nptr.end(), tile_nptr);
+    if (tile_nodes) std::copy(RP.nodes.begin(), RP.nodes.end(), tile_nodes);
+    return ok();
+}
+
 nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream) {
     if (!m || !ws) return fail(NSA_EINVAL, "nsa_mesh_upload: null argument");
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
@@ -889,7 +1044,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
             for (int64_t i = 0; i < np; i++)
                 for (int c = 0; c < 3; c++) co[c * np + i] = m->coord[3 * i + c];
         std::vector<double> co4;
-        if (m->plan[0].ok || m->plan[1].ok || m->gplan.ok) {
+        if (m->plan[0].ok || m->plan[1].ok || m->gplan.ok || m->rplan.ok) {
             co4.assign(4 * (size_t)np, 0.0);
             for (int64_t i = 0; i < np; i++)
                 for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
@@ -899,6 +1054,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         struct Up { const nsa::Region &r; const void *src; };
         const nsa::TilePlan &P0 = m->plan[0], &P1 = m->plan[1];
         const nsa::GatherPlan &G = m->gplan;
+        const nsa::ResPlan &RP = m->rplan;
         const Up ups[] = {{m->r_ln, ln.data()}, {m->r_coord, co.data()}, {m->r_emap, em.data()},
                           {m->r_ln_c, lnc.data()}, {m->r_emap_c, emc.data()},
                           {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
@@ -908,7 +1064,9 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
                           {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()},
                           {G.r_row, G.row.data()}, {G.r_nptr, G.nptr.data()}, {G.r_nodes, G.nodes.data()},
                           {G.r_eptr, G.eptr.data()}, {G.r_recs, G.recs.data()}, {G.r_pptr, G.pptr.data()},
-                          {G.r_pairs, G.pairs.data()}, {G.r_slots, G.slots.data()}};
+                          {G.r_pairs, G.pairs.data()}, {G.r_slots, G.slots.data()},
+                          {RP.r_row, RP.row.data()}, {RP.r_eptr, RP.eptr.data()}, {RP.r_nptr, RP.nptr.data()},
+                          {RP.r_nodes, RP.nodes.data()}, {RP.r_recs, RP.recs.data()}};
         for (const Up &u : ups) {
             if (!u.r.bytes) continue;
             st = hip_check(hipMemcpyAsync(w + u.r.off, u.src, u.r.bytes, hipMemcpyHostToDevice, s),
@@ -936,6 +1094,12 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m) {
     std::vector<int32_t>().swap(m->bcol);
     std::vector<int32_t>().swap(m->emap);
     std::vector<int32_t>().swap(m->colour_elems);
+    {
+        nsa::ResPlan &RP = m->rplan;
+        std::vector<int32_t>().swap(RP.elems);
+        std::vector<int32_t>().swap(RP.nodes);
+        std::vector<uint2>().swap(RP.recs);
+    }
     {
         nsa::GatherPlan &G = m->gplan;
         std::vector<int32_t>().swap(G.elems);
@@ -1389,6 +1553,59 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     return st ? st : ok();
 }
 
+
+nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
+                                 const nsa_options *opt, double *rhsid, double *dt_rho, double *mass_rho,
+                                 void *stream) {
+    if (!m) return fail(NSA_EINVAL, "nsa_assemble_residual: null mesh");
+    if (!m->ws) return fail(NSA_ESTATE, "nsa_assemble_residual: mesh not uploaded");
+    nsa_options o{};
+    if (opt) o = *opt;
+    if (o.precision != NSA_FP64 && o.precision != NSA_MIXED)
+        return fail(NSA_EINVAL, "unknown precision %d", o.precision);
+    if (o.scatter != NSA_ATOMIC) return fail(NSA_EUNSUPPORTED, "the residual path has the atomic scatter mode only");
+    if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
+    if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED)
+        return fail(NSA_EUNSUPPORTED, "the residual path has the tiled kernel only");
+    if (o.block_threads != 0 && o.block_threads != 256) return fail(NSA_EINVAL, "block_threads must be 0 or 256");
+    for (int r : o.reserved)
+        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    const nsa::ResPlan &RP = m->rplan;
+    if (!RP.ok && m->npoin > 0)
+        return fail(NSA_EUNSUPPORTED, "no residual plan (nsa_mesh_set_tiling with NSA_RESIDUAL_PLAN before upload)");
+    if (!(rho > 0.0) || !std::isfinite(rho) || !(mu >= 0.0) || !std::isfinite(mu) || !(dt > 0.0) ||
+        !std::isfinite(dt))
+        return fail(NSA_EINVAL, "need rho > 0, mu >= 0, dt > 0 (finite); got %g %g %g", rho, mu, dt);
+    if ((m->nelem > 0 && !vel) || (m->npoin > 0 && (!rhsid || !dt_rho || !mass_rho)))
+        return fail(NSA_EINVAL, "nsa_assemble_residual: null device array");
+    if (((uintptr_t)rhsid | (uintptr_t)dt_rho | (uintptr_t)mass_rho) % 8)
+        return fail(NSA_EINVAL, "outputs must be 8-byte aligned");
+    int dev = -1;
+    nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != m->device) return fail(NSA_EINVAL, "mesh uploaded on device %d, current device is %d", m->device, dev);
+    if (m->npoin == 0) return ok();
+    nsa::ResArgs a;
+    a.ntiles = RP.ntiles();
+    a.lds_bytes = RP.lds;
+    a.tile_row = (const int32_t *)(m->ws + RP.r_row.off);
+    a.tile_eptr = (const int64_t *)(m->ws + RP.r_eptr.off);
+    a.rec = (const uint2 *)(m->ws + RP.r_recs.off);
+    a.tile_nptr = (const int64_t *)(m->ws + RP.r_nptr.off);
+    a.tile_nodes = (const int32_t *)(m->ws + RP.r_nodes.off);
+    a.coord = (const double4 *)(m->ws + m->r_coord4.off);
+    a.vel = vel;
+    a.rho = rho;
+    a.mu = mu;
+    a.dt = dt;
+    a.accumulate = o.accumulate;
+    a.rhsid = rhsid;
+    a.dt_rho = dt_rho;
+    a.mass_rho = mass_rho;
+    st = hip_check(nsa::launch_residual(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64, a,
+                                        (hipStream_t)stream), "assemble (residual)");
+    return st ? st : ok();
+}
 
 nsa_status nsa_fill_uniform(double *out, int64_t n, uint64_t seed, double lo, double hi, void *stream) {
     if (n < 0 || (n > 0 && !out)) return fail(NSA_EINVAL, "nsa_fill_uniform: bad arguments");

@@ -159,6 +159,45 @@ struct GatherPlan {
     int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
 };
 
+// Residual tiles (the explicit-residual outputs): tile t owns the contiguous rows [row[t], row[t+1]);
+// its node table is laid out as for the row tiles (owned rows first); its elements are 8-byte
+// records rec[eptr[t] .. eptr[t+1]) with the four local node ids, owned nodes first, ordered by
+// owned-node count (descending). LDS: node table (6 doubles per node), then 5 accumulators per
+// owned row (3 residual components, the tau- and the rho-weighted lumped mass).
+struct ResArgs {
+    int64_t ntiles = 0;
+    int64_t lds_bytes = 0;
+    const int32_t *tile_row = nullptr;   // [ntiles+1]
+    const int64_t *tile_eptr = nullptr;  // [ntiles+1]
+    const uint2 *rec = nullptr;
+    const int64_t *tile_nptr = nullptr;  // [ntiles+1]
+    const int32_t *tile_nodes = nullptr;
+    const double4 *coord = nullptr;
+    const double *vel = nullptr;
+    double rho = 1, mu = 0, dt = 1;
+    int32_t accumulate = 0;
+    double *rhsid = nullptr;             // [npoin][3]
+    double *dt_rho = nullptr;            // [npoin]
+    double *mass_rho = nullptr;          // [npoin]
+};
+constexpr int kResStride = 5;
+__host__ __device__ constexpr int64_t res_lds_bytes(int32_t nnod, int32_t nrows) {
+    return 48 * (int64_t)nnod + 8 * (int64_t)kResStride * nrows;
+}
+hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s);
+
+struct ResPlan {
+    int32_t tile_rows = 0;
+    bool ok = false;
+    int64_t lds = 0;
+    std::vector<int32_t> row;     // [ntiles+1]
+    std::vector<int64_t> eptr, nptr;
+    std::vector<int32_t> nodes, elems;
+    std::vector<uint2> recs;
+    Region r_row, r_eptr, r_nptr, r_nodes, r_recs;
+    int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
+};
+
 // A row-tile plan for one scatter mode (host copy, then device regions after upload).
 struct TilePlan {
     int32_t tile_blocks = 0;     // requested tile size: LDS budget tile_blocks * 160 bytes
@@ -199,6 +238,8 @@ struct nsa_mesh {
     int32_t want_blocks[2] = {0, 0};
     nsa::GatherPlan gplan;              // gather tiles (both scatter modes, both precisions)
     int32_t want_gather = 0;
+    nsa::ResPlan rplan;                 // residual tiles (explicit-residual outputs)
+    int32_t want_res = 0;
     bool planned = false;
     bool keep_direct = true;            // upload the direct kernel's SoA arrays
     std::mutex plan_mu;

@@ -563,6 +563,125 @@ __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *desc, con
     }
 }
 
+// ================================================================================================
+// Explicit residual (the outputs of Listing 2 instead of a matrix): per owned row of an element,
+// the momentum residual RHS - sum_b A_uu(a, b) U_b (pressure zero), and the tau- and rho-weighted
+// lumped masses tau1 V/4 and rho V/4. The advection field and the previous-step velocity are the
+// same nodal field, so the RHS equals the transient parts of A_uu applied to U exactly:
+//   (rho/dt) int u N_a = sum_b (rho/dt) M_ab U_b   and   tau1 rho (rho/dt) int (a.grad N_a) u =
+//   sum_b tau1 rho (rho/dt) int (a.grad N_a) N_b U_b.
+// The residual is therefore formed directly as minus the spatial part applied to U,
+//   r_a = -sum_b [ (rho V/20 (s_b + d[a][b]) + tau1 rho^2 V/20 (s_a s_b + gram_ab) + mu V K_ab) U_b
+//                  + mu V G_b (G_a . U_b) + tau2 V G_a (G_b . U_b) ],
+// the same value without the cancellation of the two large transient terms (which costs the mixed
+// form its accuracy). An (element, owned row) pair adds five values into the tile's LDS
+// accumulators instead of 68.
+// ================================================================================================
+
+template <typename R>
+__device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, int nrows, const double *nodes,
+                                                 double *racc) {
+    const int loc[4] = {(int)(w.x & 0xffffu), (int)(w.x >> 16), (int)(w.y & 0xffffu), (int)(w.y >> 16)};
+    int nown = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) nown += loc[a] < nrows;
+    double X[4][3], U[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const double2 *nd = reinterpret_cast<const double2 *>(nodes + 6 * loc[a]);
+        const double2 q0 = nd[0], q1 = nd[1], q2 = nd[2];
+        X[a][0] = q0.x;
+        X[a][1] = q0.y;
+        X[a][2] = q1.x;
+        U[a][0] = q1.y;
+        U[a][1] = q2.x;
+        U[a][2] = q2.y;
+    }
+    Geo2 g;
+    geometry2(X, g);
+    ElemT<R> E;
+    setup_t<R>(g, U, A.rho, A.mu, A.dt, E);
+    const R mt = E.t1V * (R)0.25, mr = E.rho * E.v4;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        if (a >= nown) break;
+        const R ga[3] = {E.G[a][0], E.G[a][1], E.G[a][2]};
+        const R sa = E.s[a];
+        const R ksb = E.c1 + E.c2 * sa;
+        R r[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const R gb[3] = {E.G[b][0], E.G[b][1], E.G[b][2]};
+            const R K = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+            const R gram = E.d[0][a] * E.d[0][b] + E.d[1][a] * E.d[1][b] + E.d[2][a] * E.d[2][b] + E.d[3][a] * E.d[3][b];
+            const R Tsp = ksb * E.s[b] + E.c1 * E.d[a][b] + E.c2 * gram + E.muV * K;
+            const R gaU = ga[0] * E.U[b][0] + ga[1] * E.U[b][1] + ga[2] * E.U[b][2];
+            const R gbU = gb[0] * E.U[b][0] + gb[1] * E.U[b][1] + gb[2] * E.U[b][2];
+#pragma unroll
+            for (int c = 0; c < 3; c++) r[c] -= Tsp * E.U[b][c] + E.muV * gb[c] * gaU + E.t2V * ga[c] * gbU;
+        }
+        double *q = racc + kResStride * loc[a];
+#pragma unroll
+        for (int c = 0; c < 3; c++) lds_add(q + c, (double)r[c]);
+        lds_add(q + 3, (double)mt);
+        lds_add(q + 4, (double)mr);
+    }
+}
+
+template <typename R, int NT>
+__global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
+    extern __shared__ double smem[];
+    const int64_t per = (A.ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= A.ntiles) return;
+    const int tid = threadIdx.x;
+    const int r0 = A.tile_row[tile], nrows = A.tile_row[tile + 1] - r0;
+    const int64_t n0 = A.tile_nptr[tile];
+    const int nnod = (int)(A.tile_nptr[tile + 1] - n0);
+    double *nodes = smem;
+    double *racc = smem + 6 * (int64_t)nnod;
+    const int64_t p0 = A.tile_eptr[tile], p1 = A.tile_eptr[tile + 1];
+    int64_t p = p0 + tid;
+    uint2 cur = make_uint2(0u, 0u);
+    if (p < p1) cur = A.rec[p];
+    for (int i = tid; i < nnod; i += NT) {
+        const int64_t gnode = A.tile_nodes[n0 + i];
+        const double4 c = A.coord[gnode];
+        const double *v = A.vel + 3 * gnode;
+        double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
+        nd[0] = make_double2(c.x, c.y);
+        nd[1] = make_double2(c.z, v[0]);
+        nd[2] = make_double2(v[1], v[2]);
+    }
+    for (int i = tid; i < kResStride * nrows; i += NT) racc[i] = 0.0;
+    __syncthreads();
+    while (p < p1) {
+        const int64_t pn = p + NT;
+        uint2 nxt = make_uint2(0u, 0u);
+        if (pn < p1) nxt = A.rec[pn];
+        residual_element<R>(A, cur, nrows, nodes, racc);
+        cur = nxt;
+        p = pn;
+    }
+    __syncthreads();
+    for (int i = tid; i < 3 * nrows; i += NT) {
+        const int r = i / 3, c = i - 3 * r;
+        double v = racc[kResStride * r + c];
+        double *o = A.rhsid + 3 * (int64_t)r0 + i;
+        if (A.accumulate) v += *o;
+        *o = v;
+    }
+    for (int i = tid; i < nrows; i += NT) {
+        double t = racc[kResStride * i + 3], m = racc[kResStride * i + 4];
+        if (A.accumulate) {
+            t += A.dt_rho[r0 + i];
+            m += A.mass_rho[r0 + i];
+        }
+        A.dt_rho[r0 + i] = t;
+        A.mass_rho[r0 + i] = m;
+    }
+}
+
 }  // namespace
 
 size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
@@ -597,6 +716,20 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     if (nt == 64) return mixed ? go(k_tiled<float, 64>) : go(k_tiled<double, 64>);
     if (nt == 128) return mixed ? go(k_tiled<float, 128>) : go(k_tiled<double, 128>);
     return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
+}
+
+hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)a.lds_bytes;
+    const int64_t per = (a.ntiles + 7) / 8;
+    const dim3 grid((unsigned)(8 * per)), block(256);
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = ensure_lds(reinterpret_cast<const void *>(kern), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+        return hipGetLastError();
+    };
+    return k == TileKern::Mixed ? go(k_residual<float, 256>) : go(k_residual<double, 256>);
 }
 
 hipError_t prepare_batch(int threads, size_t lds) {

@@ -19,13 +19,14 @@ FP64, MIXED = 0, 1
 ATOMIC, COLOUR = 0, 1
 KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT, KERNEL_GATHER = 0, 1, 2, 3
 GATHER_PLAN = 2
+RESIDUAL_PLAN = 3
 
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
-           "nsa_assemble_batched", "nsa_fill_uniform"]
+           "nsa_assemble_batched", "nsa_fill_uniform", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
 
 
 class NsaError(RuntimeError):
@@ -46,7 +47,9 @@ class MeshInfo(C.Structure):
                 ("tile_threads", C.c_int32 * 2), ("tile_max_colours", C.c_int32 * 2),
                 ("tile_lds_bytes", C.c_int32 * 2), ("gather_ntiles", C.c_int64), ("gather_records", C.c_int64),
                 ("gather_pairs", C.c_int64), ("gather_tile_blocks", C.c_int32), ("gather_threads", C.c_int32),
-                ("gather_lds_bytes", C.c_int32 * 2)]
+                ("gather_lds_bytes", C.c_int32 * 2), ("residual_ntiles", C.c_int64),
+                ("residual_records", C.c_int64), ("residual_tile_rows", C.c_int32),
+                ("residual_lds_bytes", C.c_int32)]
 
 
 _lib = None
@@ -89,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.nsa_batch_set_inputs.argtypes = [P, P, P, P, P, P, P, i32, P]
     lib.nsa_assemble_batched.argtypes = [P, C.POINTER(Options), i32, P]
     lib.nsa_fill_uniform.argtypes = [P, i64, C.c_uint64, d, d, P]
+    lib.nsa_mesh_get_residual_tiles.argtypes = [P, P, P, P, P, P, P]
+    lib.nsa_assemble_residual.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P, P]
     for name in EXPORTS:
         if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
             getattr(lib, name).restype = i32
@@ -137,7 +142,7 @@ class Mesh:
 
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
                  tile_blocks_colour: int | None = None, keep_direct: bool = True,
-                 tile_blocks_gather: int | None = None):
+                 tile_blocks_gather: int | None = None, tile_rows_residual: int | None = None):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -153,14 +158,18 @@ class Mesh:
             _check(lib.nsa_mesh_set_tiling(h, COLOUR, int(tile_blocks_colour)), "nsa_mesh_set_tiling")
         if tile_blocks_gather is not None:
             _check(lib.nsa_mesh_set_tiling(h, GATHER_PLAN, int(tile_blocks_gather)), "nsa_mesh_set_tiling")
+        if tile_rows_residual is not None:
+            _check(lib.nsa_mesh_set_tiling(h, RESIDUAL_PLAN, int(tile_rows_residual)), "nsa_mesh_set_tiling")
         if not keep_direct:
             _check(lib.nsa_mesh_keep_direct(h, 0), "nsa_mesh_keep_direct")
         self.info = self._info()
 
     @classmethod
     def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None,
-                    tile_blocks_gather: int | None = None, keep_direct: bool = True) -> "Mesh":
-        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather)
+                    tile_blocks_gather: int | None = None, keep_direct: bool = True,
+                    tile_rows_residual: int | None = None) -> "Mesh":
+        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather,
+                   tile_rows_residual)
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")
@@ -239,6 +248,23 @@ class Mesh:
                "nsa_mesh_get_gather")
         return out
 
+    def residual_tiles(self):
+        """Residual plan: dict of tile_row, tile_eptr, elems, local_nodes (uint16 [records][4]),
+        tile_nptr, tile_nodes."""
+        i = self.info
+        nt, nr = i.residual_ntiles, i.residual_records
+        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_eptr=np.zeros(nt + 1, np.int64),
+                   elems=np.zeros(nr, np.int32), local_nodes=np.zeros((nr, 4), np.uint16),
+                   tile_nptr=np.zeros(nt + 1, np.int64))
+        lib = load()
+        _check(lib.nsa_mesh_get_residual_tiles(self._h, None, None, None, None, _ptr(out["tile_nptr"]), None),
+               "nsa_mesh_get_residual_tiles")
+        out["tile_nodes"] = np.zeros(int(out["tile_nptr"][-1]), np.int32)
+        _check(lib.nsa_mesh_get_residual_tiles(self._h, _ptr(out["tile_row"]), _ptr(out["tile_eptr"]),
+                                               _ptr(out["elems"]), _ptr(out["local_nodes"]), None,
+                                               _ptr(out["tile_nodes"])), "nsa_mesh_get_residual_tiles")
+        return out
+
     def upload(self, device="cuda", stream=None):
         import torch
         nbytes = int(self.info.ws_bytes)
@@ -281,6 +307,25 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
     _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
                                _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
     return values, rhs
+
+
+def assemble_residual(mesh: Mesh, vel, rho, mu, dt, precision=FP64, accumulate=False, rhsid=None, dt_rho=None,
+                      mass_rho=None, stream=None):
+    """Explicit-residual outputs (rhsid [npoin][3], dt_rho [npoin], mass_rho [npoin]) on the device;
+    outputs are allocated when not given."""
+    import torch
+    dev = vel.device if hasattr(vel, "device") else "cuda"
+    if rhsid is None:
+        rhsid = torch.empty((mesh.npoin, 3), dtype=torch.float64, device=dev)
+    if dt_rho is None:
+        dt_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
+    if mass_rho is None:
+        mass_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
+    o = make_options(precision, ATOMIC, accumulate)
+    _check(load().nsa_assemble_residual(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o),
+                                        _ptr(rhsid), _ptr(dt_rho), _ptr(mass_rho), _stream_handle(stream)),
+           "nsa_assemble_residual")
+    return rhsid, dt_rho, mass_rho
 
 
 def fill_uniform(out, seed: int, lo: float = -1.0, hi: float = 1.0, stream=None):

@@ -298,3 +298,44 @@ def test_fill_uniform_argument_checks(lib):
     assert lib.nsa_fill_uniform(8, 5, 0, 1.0, 0.0, None) == nsa.NSA_EINVAL
     assert lib.nsa_fill_uniform(8, 5, 0, float("nan"), 1.0, None) == nsa.NSA_EINVAL
     assert lib.nsa_fill_uniform(12, 5, 0, 0.0, 1.0, None) == nsa.NSA_EINVAL  # misaligned
+
+
+def check_residual_plan(m, mesh, lds_limit=64 * 1024):
+    """The residual kernel's indices stay inside its buffers: contiguous row tiles, records = the
+    elements touching the rows with owned local ids first, node tables as for the row tiles."""
+    info = mesh.info
+    t = mesh.residual_tiles()
+    tr, te, tn = t["tile_row"], t["tile_eptr"], t["tile_nptr"]
+    assert tr[0] == 0 and tr[-1] == m.npoin and np.all(np.diff(tr) > 0)
+    assert np.all(np.diff(tr) <= info.residual_tile_rows)
+    need = [48 * n + 40 * r for n, r in zip(np.diff(tn), np.diff(tr))]
+    assert info.residual_lds_bytes == max(need) <= lds_limit
+    n2e = [[] for _ in range(m.npoin)]
+    for e, nodes in enumerate(m.lnods):
+        for a in nodes:
+            n2e[a].append(e)
+    for k in range(len(tr) - 1):
+        r0, r1 = int(tr[k]), int(tr[k + 1])
+        nr = r1 - r0
+        els = t["elems"][te[k]:te[k + 1]]
+        assert sorted(els.tolist()) == sorted({e for i in range(r0, r1) for e in n2e[i]})
+        nodes = t["tile_nodes"][tn[k]:tn[k + 1]]
+        assert np.array_equal(nodes[:nr], np.arange(r0, r1)) and np.all(np.diff(nodes[nr:]) > 0)
+        loc = t["local_nodes"][te[k]:te[k + 1]].astype(np.int64)
+        assert loc.max() < nodes.size
+        assert np.array_equal(np.sort(nodes[loc], axis=1), np.sort(m.lnods[els], axis=1))
+        own = loc < nr
+        nown = own.sum(axis=1)
+        assert np.all(nown >= 1) and np.all(np.diff(nown) <= 0)
+        assert all(np.all(own[j, :nown[j]]) and not np.any(own[j, nown[j]:]) for j in range(len(els)))
+
+
+@pytest.mark.parametrize("rows", [1, 7, 64, 4096])
+def test_residual_plan_in_bounds(lib, rows):
+    m = inputs.make_mesh(5, jitter=True, permute=True, rcm=True, sort_elements=True, seed=37)
+    mesh = nsa.Mesh.from_inputs(m, tile_rows_residual=rows)
+    assert mesh.info.residual_ntiles >= 1 and mesh.info.residual_tile_rows == rows
+    check_residual_plan(m, mesh)
+    m2 = inputs.make_mesh(4, jitter=True, permute=True, seed=38)
+    check_residual_plan(m2, nsa.Mesh.from_inputs(m2, tile_rows_residual=rows))
+    assert nsa.Mesh.from_inputs(m2).info.residual_ntiles == 0, "opt-in"
