@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <thread>
+#include <unordered_map>
 
 #include "nsa_internal.h"
 
@@ -146,7 +147,10 @@ double elem_det(const int32_t *ln, const double *coord) {
 // Greedy first-fit colouring in element order with per-node colour masks (up to 128 colours).
 nsa_status colour_elements(nsa_mesh *m) {
     const int64_t n = m->nelem;
+    // colours 0..127 of every node in two inline words; colours from 128 on (nodes in more than
+    // 128 elements) in per-node overflow bitsets
     std::vector<uint64_t> mask(2 * (size_t)m->npoin, 0);
+    std::unordered_map<int32_t, std::vector<uint64_t>> extra;
     std::vector<int32_t> col(n);
     int32_t ncol = 0;
     for (int64_t e = 0; e < n; e++) {
@@ -157,13 +161,36 @@ nsa_status colour_elements(nsa_mesh *m) {
             f1 |= mask[2 * (size_t)ln[a] + 1];
         }
         int c;
-        if (~f0)
+        if (~f0) {
             c = __builtin_ctzll(~f0);
-        else if (~f1)
+        } else if (~f1) {
             c = 64 + __builtin_ctzll(~f1);
-        else
-            return fail(NSA_EUNSUPPORTED, "element %lld needs more than 128 colours", (long long)e);
-        for (int a = 0; a < 4; a++) mask[2 * (size_t)ln[a] + (c >> 6)] |= 1ull << (c & 63);
+        } else {
+            size_t words = 0;
+            for (int a = 0; a < 4; a++) {
+                auto it = extra.find(ln[a]);
+                if (it != extra.end()) words = std::max(words, it->second.size());
+            }
+            c = -1;
+            for (size_t w = 0; w <= words && c < 0; w++) {
+                uint64_t f = 0;
+                for (int a = 0; a < 4; a++) {
+                    auto it = extra.find(ln[a]);
+                    if (it != extra.end() && w < it->second.size()) f |= it->second[w];
+                }
+                if (~f) c = 128 + 64 * (int)w + __builtin_ctzll(~f);
+            }
+        }
+        for (int a = 0; a < 4; a++) {
+            if (c < 128) {
+                mask[2 * (size_t)ln[a] + (c >> 6)] |= 1ull << (c & 63);
+            } else {
+                std::vector<uint64_t> &x = extra[ln[a]];
+                const size_t w = (size_t)(c - 128) >> 6;
+                if (x.size() <= w) x.resize(w + 1, 0);
+                x[w] |= 1ull << ((c - 128) & 63);
+            }
+        }
         col[e] = c;
         ncol = std::max(ncol, c + 1);
     }
@@ -257,7 +284,6 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
         std::vector<nsa::TileRec> recs;
         std::vector<int64_t> cnt, ncnt;  // per tile record / node counts
         int32_t maxcol = 0;
-        bool too_many = false;
     };
     std::vector<Out> outs(host_threads());
     int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
@@ -301,15 +327,17 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
                     f0 |= mask[2 * l];
                     f1 |= mask[2 * l + 1];
                 }
+                // more than 127 colours (an owned node in more than 127 of the tile's elements):
+                // the rest share colour 127. Tile colours only order the records (the atomics keep
+                // the sums right, the one-wavefront plan keeps them reproducible), so this costs
+                // some same-block collisions inside an instruction, nothing else.
                 int c;
                 if (~f0)
                     c = __builtin_ctzll(~f0);
-                else if (~f1)
+                else if (~f1 && __builtin_ctzll(~f1) < 63)
                     c = 64 + __builtin_ctzll(~f1);
-                else {
-                    o.too_many = true;
-                    return;
-                }
+                else
+                    c = 127;
                 for (int a = 0; a < 4; a++) {
                     int32_t l = ln[a] - r0;
                     if (l >= 0 && l < nr) mask[2 * l + (c >> 6)] |= 1ull << (c & 63);
@@ -346,8 +374,6 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
             o.cnt.push_back((int64_t)ne);
         }
     });
-    for (int i = 0; i < used; i++)
-        if (outs[i].too_many) return fail(NSA_EUNSUPPORTED, "a tile needs more than 128 colours");
     P.eptr.assign(1, 0);
     P.nptr.assign(1, 0);
     for (int i = 0; i < used; i++) {

@@ -254,3 +254,34 @@ def served_requests(nreq: int, nmesh: int, rate: float, seed: int = 6):
     vseed = rng.integers(0, 2 ** 62, size=nreq)
     return [dict(t=float(t[i]), mesh=int(mesh[i]), rho=float(rho[i]), mu=float(mu[i]), dt=float(dt[i]),
                  vel_seed=int(vseed[i])) for i in range(nreq)]
+
+
+def hub_mesh(level: int = 4, seed: int = 0, rho: float = 1.0, mu: float = 1e-3, dt: float = 1e-2) -> Mesh:
+    """A fan of tets around one hub node: the octahedron's faces split `level` times into four,
+    pushed to the unit sphere, each surface triangle joined to the centre. The hub's block row has
+    one block per surface vertex plus its own (4^level * 4 + 2 + 1 = 1027 at level 4), far beyond
+    what a row tile holds; every other row has about eight. Velocity U[-1,1]^3 per node."""
+    rng = np.random.default_rng(seed)
+    verts = [np.array(v, dtype=np.float64) for v in
+             ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))]
+    faces = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                p = verts[i] + verts[j]
+                verts.append(p / np.linalg.norm(p))
+                mid[key] = len(verts) - 1
+            return mid[key]
+        new = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            new += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+        faces = new
+    surf = np.array(verts) * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=(len(verts), 1)))
+    coord = np.vstack([np.zeros((1, 3)), surf])
+    lnods = np.array([(0, a + 1, b + 1, c + 1) for a, b, c in faces], dtype=np.int32)
+    velocity = rng.uniform(-1.0, 1.0, size=coord.shape)
+    return Mesh(n=level, lnods=lnods, coord=coord, velocity=velocity, rho=rho, mu=mu, dt=dt, name=f"hub{level}")

@@ -216,3 +216,32 @@ def test_gather_bitwise_independent_of_tiling_and_mode():
                 if base is None:
                     base = (v, r)
                 assert np.array_equal(v, base[0]) and np.array_equal(r, base[1]), (prec, tb, nt, scatter)
+
+
+@pytest.mark.parametrize("level", [2, 4])
+def test_high_degree_hub(level):
+    """A node in 128 / 2048 elements: every kernel the mesh supports (the row-tiled one only for
+    rows up to 256 blocks; the direct one with 128 / 2048 global colours; the residual path)
+    against the oracle."""
+    m = inputs.hub_mesh(level, seed=level)
+    say(f"[parity] hub level {level} nelem={m.nelem}")
+    ref_v, ref_r = oracle.assemble(m)
+    ref_res = oracle.residual(m)
+    mesh = nsa.Mesh.from_inputs(m, tile_rows_residual=64, tile_blocks_gather=512).upload()
+    kernels = [nsa.KERNEL_AUTO, nsa.KERNEL_DIRECT]
+    if mesh.info.ntiles[0]:
+        kernels.append(nsa.KERNEL_TILED)
+    if mesh.info.gather_ntiles:
+        kernels.append(nsa.KERNEL_GATHER)
+    for kernel in kernels:
+        for mode in MODES:
+            v, r = gpu_assemble(mesh, m, *mode, kernel=kernel)
+            assert_parity(v, ref_v, r, ref_r, tol_of(mode[0]), f"hub {level} {mode} kernel={kernel}")
+    if not mesh.info.ntiles[0]:
+        with pytest.raises(nsa.NsaError):
+            gpu_assemble(mesh, m, nsa.FP64, nsa.ATOMIC, kernel=nsa.KERNEL_TILED)
+    vel = torch.from_numpy(m.velocity).cuda()
+    for prec in (nsa.FP64, nsa.MIXED):
+        got = [x.cpu().numpy() for x in nsa.assemble_residual(mesh, vel, m.rho, m.mu, m.dt, precision=prec)]
+        for g, ref in zip(got, ref_res):
+            assert np.abs(g - ref).max() <= tol_of(prec) * np.abs(ref).max()

@@ -117,7 +117,7 @@ def test_isolated_nodes_match_oracle(lib):
     assert mb[11] == mb[10]
 
 
-def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
+def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024, overflow_colour=None):
     """Every index the tiled kernel derives from the plan stays inside its buffers, and the record
     order is the one the mode relies on."""
     info = mesh.info
@@ -151,6 +151,8 @@ def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
         else:
             assert np.all(np.diff(cols) >= 0), "deterministic order: tile colour ascending"
         for c in np.unique(cols):
+            if c == overflow_colour:
+                continue  # the shared colour of a tile that needs more than 127
             nodes = m.lnods[els[cols == c]].ravel()
             owned = nodes[(nodes >= r0) & (nodes < r1)]
             assert np.unique(owned).size == owned.size, f"tile {k} colour {c} shares an owned node"
@@ -339,3 +341,30 @@ def test_residual_plan_in_bounds(lib, rows):
     m2 = inputs.make_mesh(4, jitter=True, permute=True, seed=38)
     check_residual_plan(m2, nsa.Mesh.from_inputs(m2, tile_rows_residual=rows))
     assert nsa.Mesh.from_inputs(m2).info.residual_ntiles == 0, "opt-in"
+
+
+@pytest.mark.parametrize("level", [2, 3, 4])
+def test_high_degree_hub(lib, level):
+    """A node in 128 / 512 / 2048 elements (rows of 67 / 259 / 1027 blocks): the global colouring
+    grows past 128 colours and stays valid; rows over 256 blocks leave the mesh without row tiles
+    (the direct kernel serves it), a tile that needs more than 127 colours shares its last one."""
+    m = inputs.hub_mesh(level, seed=level)
+    mesh = nsa.Mesh.from_inputs(m, tile_rows_residual=64)
+    info = mesh.info
+    b, c, e = mesh.pattern()
+    ob, oc, oe = oracle.pattern(m.npoin, m.lnods)
+    assert np.array_equal(b, ob) and np.array_equal(c, oc) and np.array_equal(e, oe)
+    assert info.ncolours >= m.nelem  # every element shares the hub
+    cp, ce = mesh.colouring()
+    assert np.array_equal(np.sort(ce), np.arange(m.nelem))
+    for k in range(len(cp) - 1):
+        nodes = m.lnods[ce[cp[k]:cp[k + 1]]].ravel()
+        assert np.unique(nodes).size == nodes.size
+    if info.max_row_blocks > 256:
+        assert list(info.ntiles) == [0, 0]
+    else:
+        for scatter in (nsa.ATOMIC, nsa.COLOUR):
+            assert info.tile_max_colours[scatter] <= 128
+            check_tile_plan(m, mesh, scatter, overflow_colour=127)
+    assert info.residual_ntiles >= 1
+    check_residual_plan(m, mesh)
