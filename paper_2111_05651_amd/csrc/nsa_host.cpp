@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -230,15 +231,126 @@ int parallel_chunks(int64_t n, F f) {
     return used;
 }
 
+// Throughput-plan record order: groups of 16 consecutive records (the lanes whose 8-byte LDS atomics
+// the LDS serves together: 16 lanes over 32 four-byte banks) chosen so that, for each owned-row
+// iteration k and column b, the blocks the lanes add into sit on different bank pairs (value i of
+// block slot s of the tile lies on bank pair (17 s + i) mod 16) and in different rows (same row:
+// same diagonal block, same address). Each record may take its owned
+// rows in any order and its other vertices in any order; the chosen vertex order is written back to
+// vord. Records stay grouped by owned-row count; each half-wavefront slot takes, among the next few
+// records of the group, the one (and vertex order) that adds the least to the lanes already placed.
+void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::vector<int32_t> &nown, int32_t r0,
+                const std::vector<int32_t> &base, std::vector<int8_t> &vord, std::vector<int32_t> &out) {
+    constexpr int kWindow = 8;
+    const size_t ne = base.size();
+    out.clear();
+    out.reserve(ne);
+    const int64_t b0 = m->bptr[r0];
+    constexpr int kGroup = 16;
+    uint8_t cnt[4][4][kGroup], peak[4][4];
+    uint32_t rows[4][2];  // rows used per iteration k (local rows < 64 tracked, others ignored)
+    int fill = kGroup;
+    // all vertex orders of a record: owned part permuted, then the other part permuted
+    auto orders = [&](int32_t j, int8_t (*cand)[4]) -> int {
+        int8_t o[4], x[4];
+        const int n = nown[j];
+        for (int q = 0; q < 4; q++) (q < n ? o[q] : x[q - n]) = vord[4 * j + q];
+        std::sort(o, o + n);
+        std::sort(x, x + 4 - n);
+        int c = 0;
+        do {
+            int8_t xx[4];
+            std::copy(x, x + 4 - n, xx);
+            do {
+                if (c == 24) return c;
+                for (int q = 0; q < n; q++) cand[c][q] = o[q];
+                for (int q = n; q < 4; q++) cand[c][q] = xx[q - n];
+                c++;
+            } while (std::next_permutation(xx, xx + 4 - n));
+        } while (std::next_permutation(o, o + n));
+        return c;
+    };
+    // cost of placing record j with vertex order v: a row already used by iteration k (same diagonal
+    // block), then for each (k, b) the lanes already on that bank pair, heavily if the record would
+    // raise the instruction's worst bank pair (the LDS needs one pass per lane on that pair)
+    auto cost = [&](int32_t j, const int8_t *v) -> int {
+        const int64_t e = els[j];
+        const int32_t *ln = &m->lnods[4 * e];
+        int c = 0;
+        for (int k = 0; k < nown[j]; k++) {
+            const int lr = ln[v[k]] - r0;
+            if (lr < 64 && ((rows[k][lr >> 5] >> (lr & 31)) & 1u)) c += 64;
+            for (int b = 0; b < 4; b++) {
+                const int64_t slot = m->emap[16 * e + 4 * v[k] + v[b]] - b0;
+                const int n = cnt[k][b][slot & (kGroup - 1)];
+                c += n >= peak[k][b] ? 16 * (n + 1) : n;
+            }
+        }
+        return c;
+    };
+    auto place = [&](int32_t j, const int8_t *v) {
+        const int64_t e = els[j];
+        const int32_t *ln = &m->lnods[4 * e];
+        for (int k = 0; k < nown[j]; k++) {
+            const int lr = ln[v[k]] - r0;
+            if (lr < 64) rows[k][lr >> 5] |= 1u << (lr & 31);
+            for (int b = 0; b < 4; b++) {
+                const int64_t slot = m->emap[16 * e + 4 * v[k] + v[b]] - b0;
+                const int n = ++cnt[k][b][slot & (kGroup - 1)];
+                peak[k][b] = std::max<int>(peak[k][b], n);
+            }
+        }
+        for (int q = 0; q < 4; q++) vord[4 * j + q] = v[q];
+        out.push_back(j);
+        fill++;
+    };
+    std::vector<int32_t> pool;
+    int8_t cand[24][4];
+    size_t g0 = 0;
+    while (g0 < ne) {
+        size_t g1 = g0;
+        while (g1 < ne && nown[base[g1]] == nown[base[g0]]) g1++;
+        pool.assign(base.begin() + g0, base.begin() + g1);
+        g0 = g1;
+        size_t head = 0;  // pool[head ..] remain, in base order
+        while (head < pool.size()) {
+            if (fill == kGroup) {
+                std::memset(cnt, 0, sizeof(cnt));
+                std::memset(peak, 0, sizeof(peak));
+                std::memset(rows, 0, sizeof(rows));
+                fill = 0;
+            }
+            size_t best = head;
+            int bestc = 1 << 30;
+            int8_t bestv[4] = {0, 1, 2, 3};
+            for (size_t q = head; q < pool.size() && q < head + kWindow; q++) {
+                const int nc = orders(pool[q], cand);
+                for (int c = 0; c < nc; c++) {
+                    const int v = cost(pool[q], cand[c]);
+                    if (v < bestc) {
+                        bestc = v;
+                        best = q;
+                        std::copy(cand[c], cand[c] + 4, bestv);
+                    }
+                }
+                if (!bestc) break;
+            }
+            place(pool[best], bestv);
+            std::swap(pool[best], pool[head]);
+            head++;
+        }
+    }
+}
+
 // Row tiles for the tiled kernel (see nsa_internal.h). A tile is a contiguous row range whose LDS
 // footprint (block image, RHS rows, row offsets, node table) stays within tile_blocks * 160 bytes.
 // Per tile: the nodes its elements touch (the owned rows first, as local ids 0 .. nrows-1, then the
 // other nodes ascending), a greedy colouring of its elements (elements of one tile colour share no
 // owned node), and one 24-byte record per element with its local node ids (owned nodes first) and
 // the in-row ranks of its owned rows. Record order: for the throughput plan, owned-row count
-// descending (the lanes of a wavefront run the same number of row iterations) then colour (lanes
-// of one instruction rarely add into the same LDS block); for the deterministic plan, colour, then
-// owned-row count descending.
+// descending (the lanes of a wavefront run the same number of row iterations), then the bank-aware
+// order of bank_order() inside each count; for the deterministic plan, colour (elements of one
+// colour share no owned node), then owned-row count descending.
 nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads, bool colour_first) {
     P = nsa::TilePlan();
     P.tile_blocks = tile_blocks;
@@ -288,7 +400,8 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
     std::vector<Out> outs(host_threads());
     int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
         Out &o = outs[ci];
-        std::vector<int32_t> els, col, nown, idx, other;
+        std::vector<int32_t> els, col, nown, idx, other, sched;
+        std::vector<int8_t> vord;
         std::vector<uint64_t> mask;
         for (int64_t t = tb; t < te; t++) {
             const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
@@ -353,14 +466,25 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
                 if (col[x] != col[y]) return col[x] < col[y];
                 return els[x] < els[y];
             });
+            // vertex order of each record: owned first (ascending), then the others
+            vord.resize(4 * ne);
+            for (size_t j = 0; j < ne; j++) {
+                const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
+                int k = 0;
+                for (int a = 0; a < 4; a++)
+                    if (ln[a] >= r0 && ln[a] < r1) vord[4 * j + k++] = (int8_t)a;
+                for (int a = 0; a < 4; a++)
+                    if (!(ln[a] >= r0 && ln[a] < r1)) vord[4 * j + k++] = (int8_t)a;
+            }
+            if (!colour_first) {
+                bank_order(m, els, nown, r0, idx, vord, sched);
+                idx.swap(sched);
+            }
             for (int32_t j : idx) {
                 const int64_t e = els[j];
                 const int32_t *ln = &m->lnods[4 * e];
-                int ord[4], k = 0;
-                for (int a = 0; a < 4; a++)
-                    if (ln[a] >= r0 && ln[a] < r1) ord[k++] = a;
-                for (int a = 0; a < 4; a++)
-                    if (!(ln[a] >= r0 && ln[a] < r1)) ord[k++] = a;
+                int ord[4];
+                for (int q = 0; q < 4; q++) ord[q] = vord[4 * j + q];
                 nsa::TileRec r{};
                 for (int q = 0; q < 4; q++) r.loc[q] = (uint16_t)local(ln[ord[q]]);
                 for (int q = 0; q < nown[j]; q++) {

@@ -284,6 +284,10 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 // global atomics, no zero-fill pass, and every value line is written exactly once. Elements on a
 // tile boundary are evaluated by each tile they touch; only their owned rows are integrated there.
 //
+// The LDS atomics set the pace: the LDS serves an 8-byte atomic 16 lanes at a time, one pass per
+// lane on the busiest bank pair, so the throughput plan orders its records such that the 16 lanes
+// of each group add into blocks on distinct bank pairs as far as it can (host planner).
+//
 // Two plans use this kernel. The throughput plan gives a tile to a workgroup of four wavefronts;
 // the order in which their LDS atomics land on one block varies from run to run. The deterministic
 // plan gives each (smaller) tile to a single wavefront: every LDS word of the tile is then updated
