@@ -61,9 +61,9 @@ typedef int32_t nsa_status;
 #define NSA_ATOMIC 0           /* FP64 atomic adds from concurrent threads (throughput mode; the
                                   order of the additions, hence the last bits, may vary by run) */
 #define NSA_COLOUR 1           /* deterministic, bit-reproducible: the tiled kernel processes each
-                                  tile's elements in tile-colour order inside a single wavefront
-                                  (elements of one colour share no owned node); the direct kernel
-                                  runs one global colour class at a time with plain load-add-store */
+                                  tile's elements in the plan's fixed order inside a single
+                                  wavefront; the direct kernel runs one global colour class at a
+                                  time with plain load-add-store */
 
 /* kernel family */
 #define NSA_KERNEL_AUTO 0      /* the row-tiled kernel when the mesh allows it, else the direct one */

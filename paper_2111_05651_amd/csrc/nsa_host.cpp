@@ -231,7 +231,7 @@ int parallel_chunks(int64_t n, F f) {
     return used;
 }
 
-// Throughput-plan record order: groups of 16 consecutive records (the lanes whose 8-byte LDS atomics
+// Record order of a tile: groups of 16 consecutive records (the lanes whose 8-byte LDS atomics
 // the LDS serves together: 16 lanes over 32 four-byte banks) chosen so that, for each owned-row
 // iteration k and column b, the blocks the lanes add into sit on different bank pairs (value i of
 // block slot s of the tile lies on bank pair (17 s + i) mod 16) and in different rows (same row:
@@ -347,11 +347,11 @@ void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::v
 // Per tile: the nodes its elements touch (the owned rows first, as local ids 0 .. nrows-1, then the
 // other nodes ascending), a greedy colouring of its elements (elements of one tile colour share no
 // owned node), and one 24-byte record per element with its local node ids (owned nodes first) and
-// the in-row ranks of its owned rows. Record order: for the throughput plan, owned-row count
-// descending (the lanes of a wavefront run the same number of row iterations), then the bank-aware
-// order of bank_order() inside each count; for the deterministic plan, colour (elements of one
-// colour share no owned node), then owned-row count descending.
-nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads, bool colour_first) {
+// the in-row ranks of its owned rows. Record order (both plans): owned-row count descending (the
+// lanes of a wavefront run the same number of row iterations), then the bank-aware order of
+// bank_order() inside each count. The deterministic plan needs no particular order: one wavefront
+// integrates the tile, so its LDS adds happen in the plan's fixed order whatever that order is.
+nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads) {
     P = nsa::TilePlan();
     P.tile_blocks = tile_blocks;
     P.threads = threads;
@@ -441,9 +441,9 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
                     f1 |= mask[2 * l + 1];
                 }
                 // more than 127 colours (an owned node in more than 127 of the tile's elements):
-                // the rest share colour 127. Tile colours only order the records (the atomics keep
-                // the sums right, the one-wavefront plan keeps them reproducible), so this costs
-                // some same-block collisions inside an instruction, nothing else.
+                // the rest share colour 127. Tile colours are reported with the plan and only seed
+                // the record order (the atomics keep the sums right, the one-wavefront plan keeps
+                // them reproducible), so this costs nothing else.
                 int c;
                 if (~f0)
                     c = __builtin_ctzll(~f0);
@@ -461,7 +461,6 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
             idx.resize(ne);
             for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
             std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-                if (colour_first && col[x] != col[y]) return col[x] < col[y];
                 if (nown[x] != nown[y]) return nown[x] > nown[y];
                 if (col[x] != col[y]) return col[x] < col[y];
                 return els[x] < els[y];
@@ -476,10 +475,8 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
                 for (int a = 0; a < 4; a++)
                     if (!(ln[a] >= r0 && ln[a] < r1)) vord[4 * j + k++] = (int8_t)a;
             }
-            if (!colour_first) {
-                bank_order(m, els, nown, r0, idx, vord, sched);
-                idx.swap(sched);
-            }
+            bank_order(m, els, nown, r0, idx, vord, sched);
+            idx.swap(sched);
             for (int32_t j : idx) {
                 const int64_t e = els[j];
                 const int32_t *ln = &m->lnods[4 * e];
@@ -844,7 +841,7 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
     try {
         for (int k = 0; k < 2; k++) {
             if (m->want_blocks[k] > 0) {
-                nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], kPlanThreads[k], k == NSA_COLOUR);
+                nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], kPlanThreads[k]);
                 if (st) return st;
             } else {
                 m->plan[k] = nsa::TilePlan();

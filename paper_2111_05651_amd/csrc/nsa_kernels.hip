@@ -292,9 +292,8 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 // the order in which their LDS atomics land on one block varies from run to run. The deterministic
 // plan gives each (smaller) tile to a single wavefront: every LDS word of the tile is then updated
 // only by that wavefront's instructions, which the LDS executes in issue order, lanes of one
-// instruction in a fixed order, so the sums are bit-reproducible. Its records are ordered by
-// tile-local element colour (elements of one colour share no owned node), so the lanes of one
-// instruction rarely target the same block.
+// instruction in a fixed order, so the sums are bit-reproducible; its records take the same
+// bank-aware order as the throughput plan's.
 // ================================================================================================
 namespace {
 

@@ -146,10 +146,7 @@ def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024, overflow_colour=None
         want = sorted({e for i in range(r0, r1) for e in n2e[i]})
         assert sorted(els) == want
         own = ((m.lnods[els] >= r0) & (m.lnods[els] < r1)).sum(axis=1)
-        if scatter == nsa.ATOMIC:
-            assert np.all(np.diff(own) <= 0), "throughput order: owned-row count descending"
-        else:
-            assert np.all(np.diff(cols) >= 0), "deterministic order: tile colour ascending"
+        assert np.all(np.diff(own) <= 0), "record order: owned-row count descending"
         for c in np.unique(cols):
             if c == overflow_colour:
                 continue  # the shared colour of a tile that needs more than 127
