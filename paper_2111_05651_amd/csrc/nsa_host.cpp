@@ -239,8 +239,11 @@ int parallel_chunks(int64_t n, F f) {
 // rows in any order and its other vertices in any order; the chosen vertex order is written back to
 // vord. Records stay grouped by owned-row count; each half-wavefront slot takes, among the next few
 // records of the group, the one (and vertex order) that adds the least to the lanes already placed.
+// by_row: the adds of owned-row iteration k go to per-row accumulators (the residual tiles: double
+// 5 r + c of the tile's accumulators, bank pair (5 r + c) mod 16), so the bank pair of a lane follows
+// its row alone and only the order of the owned rows matters.
 void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::vector<int32_t> &nown, int32_t r0,
-                const std::vector<int32_t> &base, std::vector<int8_t> &vord, std::vector<int32_t> &out) {
+                bool by_row, const std::vector<int32_t> &base, std::vector<int8_t> &vord, std::vector<int32_t> &out) {
     constexpr int kWindow = 8;
     const size_t ne = base.size();
     out.clear();
@@ -266,7 +269,7 @@ void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::v
                 for (int q = 0; q < n; q++) cand[c][q] = o[q];
                 for (int q = n; q < 4; q++) cand[c][q] = xx[q - n];
                 c++;
-            } while (std::next_permutation(xx, xx + 4 - n));
+            } while (!by_row && std::next_permutation(xx, xx + 4 - n));
         } while (std::next_permutation(o, o + n));
         return c;
     };
@@ -281,7 +284,7 @@ void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::v
             const int lr = ln[v[k]] - r0;
             if (lr < 64 && ((rows[k][lr >> 5] >> (lr & 31)) & 1u)) c += 64;
             for (int b = 0; b < 4; b++) {
-                const int64_t slot = m->emap[16 * e + 4 * v[k] + v[b]] - b0;
+                const int64_t slot = by_row ? 5 * lr : m->emap[16 * e + 4 * v[k] + v[b]] - b0;
                 const int n = cnt[k][b][slot & (kGroup - 1)];
                 c += n >= peak[k][b] ? 16 * (n + 1) : n;
             }
@@ -295,7 +298,7 @@ void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::v
             const int lr = ln[v[k]] - r0;
             if (lr < 64) rows[k][lr >> 5] |= 1u << (lr & 31);
             for (int b = 0; b < 4; b++) {
-                const int64_t slot = m->emap[16 * e + 4 * v[k] + v[b]] - b0;
+                const int64_t slot = by_row ? 5 * lr : m->emap[16 * e + 4 * v[k] + v[b]] - b0;
                 const int n = ++cnt[k][b][slot & (kGroup - 1)];
                 peak[k][b] = std::max<int>(peak[k][b], n);
             }
@@ -475,7 +478,7 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
                 for (int a = 0; a < 4; a++)
                     if (!(ln[a] >= r0 && ln[a] < r1)) vord[4 * j + k++] = (int8_t)a;
             }
-            bank_order(m, els, nown, r0, idx, vord, sched);
+            bank_order(m, els, nown, r0, false, idx, vord, sched);
             idx.swap(sched);
             for (int32_t j : idx) {
                 const int64_t e = els[j];
@@ -682,8 +685,9 @@ nsa_status build_gather(nsa_mesh *m, nsa::GatherPlan &P, int32_t tile_blocks, in
 // Residual tiles (see nsa_internal.h): contiguous row ranges of at most tile_rows rows whose LDS
 // (48 bytes per touched node, 40 per owned row) stays within kResLds (two workgroups per CU or
 // more). Records: the elements touching the tile, local node ids owned nodes first, ordered by
-// owned-node count (descending) then element id, so that the lanes of a wavefront run the same
-// number of row iterations.
+// owned-node count (descending; the lanes of a wavefront run the same number of row iterations),
+// then by bank_order() with per-row accumulators: the 16 lanes of a group add into rows distinct
+// mod 16 where the tile allows it, so their five accumulator adds touch distinct bank pairs.
 constexpr int64_t kResLds = 64 * 1024;
 constexpr int32_t kMaxResRows = 4096;
 
@@ -724,7 +728,8 @@ nsa_status build_rtiles(nsa_mesh *m, nsa::ResPlan &P, int32_t tile_rows) {
     std::vector<Out> outs(host_threads());
     int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
         Out &o = outs[ci];
-        std::vector<int32_t> els, other, nown, idx;
+        std::vector<int32_t> els, other, nown, idx, sched;
+        std::vector<int8_t> vord;
         for (int64_t t = tb; t < te; t++) {
             const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
             els.clear();
@@ -756,14 +761,22 @@ nsa_status build_rtiles(nsa_mesh *m, nsa::ResPlan &P, int32_t tile_rows) {
             idx.resize(ne);
             for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
             std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return nown[x] > nown[y]; });
+            // vertex order: owned first, then the others; then the bank-aware order by row
+            vord.resize(4 * ne);
+            for (size_t j = 0; j < ne; j++) {
+                const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
+                int k = 0;
+                for (int a = 0; a < 4; a++)
+                    if (ln[a] >= r0 && ln[a] < r1) vord[4 * j + k++] = (int8_t)a;
+                for (int a = 0; a < 4; a++)
+                    if (!(ln[a] >= r0 && ln[a] < r1)) vord[4 * j + k++] = (int8_t)a;
+            }
+            bank_order(m, els, nown, r0, true, idx, vord, sched);
+            idx.swap(sched);
             for (int32_t j : idx) {
                 const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
                 uint32_t l[4];
-                int k = 0;
-                for (int a = 0; a < 4; a++)
-                    if (ln[a] >= r0 && ln[a] < r1) l[k++] = local(ln[a]);
-                for (int a = 0; a < 4; a++)
-                    if (!(ln[a] >= r0 && ln[a] < r1)) l[k++] = local(ln[a]);
+                for (int q = 0; q < 4; q++) l[q] = local(ln[vord[4 * j + q]]);
                 o.recs.push_back(make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16));
                 o.els.push_back(els[j]);
             }
@@ -1680,10 +1693,7 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     for (int r : o.reserved)
         if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
     const int64_t total = b->ntiles;
-    if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
-    int64_t g = grid_wgs ? grid_wgs : (int64_t)b->ncu * (b->threads == 64 ? 4 : 2);
-    g = std::min<int64_t>(g, (total + 7) / 8 * 8);
-    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    if (grid_wgs != 0) return fail(NSA_EINVAL, "grid_wgs must be 0 (one workgroup per work item)");
     int dev = -1;
     nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st) return st;
@@ -1695,7 +1705,7 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     st = hip_check(nsa::launch_tiled_batch(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64,
                                            (const nsa::TileArgs *)(b->ws + b->r_desc.off),
                                            (const int2 *)(b->ws + b->r_work.off), total, threads, b->lds,
-                                           (int)g, (hipStream_t)stream),
+                                           (hipStream_t)stream),
                    "assemble (batched)");
     return st ? st : ok();
 }

@@ -87,10 +87,10 @@ __host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows
 enum class TileKern { F64, Mixed };
 size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);
-// Batched persistent form: desc[mesh] in device memory, work[t] = (mesh, local tile).
+// Batched form: desc[mesh] in device memory, work[t] = (mesh, local tile); one workgroup per item.
 hipError_t prepare_batch(int threads, size_t lds);
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
-                              int64_t lds, int grid_wgs, hipStream_t s);
+                              int64_t lds, hipStream_t s);
 
 hipError_t ensure_lds(const void *kern, size_t bytes);
 
@@ -162,7 +162,7 @@ struct GatherPlan {
 // Residual tiles (the explicit-residual outputs): tile t owns the contiguous rows [row[t], row[t+1]);
 // its node table is laid out as for the row tiles (owned rows first); its elements are 8-byte
 // records rec[eptr[t] .. eptr[t+1]) with the four local node ids, owned nodes first, ordered by
-// owned-node count (descending). LDS: node table (6 doubles per node), then 5 accumulators per
+// owned-node count (descending), then so that each group of 16 takes rows distinct mod 16. LDS: node table (6 doubles per node), then 5 accumulators per
 // owned row (3 residual components, the tau- and the rho-weighted lumped mass).
 struct ResArgs {
     int64_t ntiles = 0;

@@ -548,22 +548,36 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     run_tile<R, NT>(A, tile, smem);
 }
 
-// Persistent batched form: a grid of resident workgroups walks the tiles of many meshes. work[t] =
-// (mesh, tile of that mesh) with each mesh's tiles contiguous; desc[mesh] holds that mesh's
-// arrays, outputs and parameters. Workgroup w runs on XCD w % 8; XCD x owns the contiguous slice
-// [x*per, (x+1)*per) of the work table and its workgroups take every (G/8)-th tile of it.
+// Batched form: one launch over the tiles of many meshes. work[t] = (mesh, tile of that mesh) with
+// each mesh's tiles contiguous; desc[mesh] holds that mesh's arrays, outputs and parameters. One
+// workgroup per work item, XCD-aware as in k_tiled: workgroup w runs on XCD w % 8, and XCD x takes the
+// contiguous slice [x*per, (x+1)*per) of the work table. (A persistent grid walking the table was
+// slower: the loop kept more of the tile body's state live and the FP64 form spilled.)
+// A member's arguments as wavefront-uniform values: every lane loads the same words, and
+// readfirstlane keeps them in scalar registers for the whole tile (a plain copy would hold them in
+// vector registers, which the FP64 element code needs).
+__device__ __forceinline__ TileArgs uniform_args(const TileArgs *p) {
+    static_assert(sizeof(TileArgs) % 4 == 0, "TileArgs is a whole number of words");
+    constexpr int kWords = (int)(sizeof(TileArgs) / 4);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t w[kWords];
+#pragma unroll
+    for (int i = 0; i < kWords; i++) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    TileArgs a;
+    __builtin_memcpy(&a, w, sizeof a);
+    return a;
+}
+
 template <typename R, int NT>
-__global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *desc, const int2 *work, int64_t total) {
+__global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restrict__ desc, const int2 *__restrict__ work,
+                                                      int64_t total) {
     extern __shared__ double smem[];
-    const int64_t nslot = gridDim.x >> 3;
     const int64_t per = (total + 7) / 8;
-    const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
-    const int64_t hi = lo + per < total ? lo + per : total;
-    for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nslot) {
-        const int2 w = work[t];
-        const TileArgs A = desc[w.x];
-        run_tile<R, NT>(A, w.y, smem);
-    }
+    const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= total) return;
+    const int2 w = make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
+    const TileArgs A = uniform_args(desc + w.x);
+    run_tile<R, NT>(A, w.y, smem);
 }
 
 // ================================================================================================
@@ -749,10 +763,10 @@ hipError_t prepare_batch(int threads, size_t lds) {
 }
 
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
-                              int64_t lds, int grid_wgs, hipStream_t s) {
+                              int64_t lds, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     const int nt = (threads == 64 || threads == 128) ? threads : 256;
-    const dim3 grid((unsigned)grid_wgs), block(nt);
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(nt);
     const bool mixed = k == TileKern::Mixed;
 #define NSA_LAUNCH_BATCH(T, N) \
     hipLaunchKernelGGL((k_tiled_batch<T, N>), grid, block, (size_t)lds, s, desc, work, total)

@@ -339,7 +339,7 @@ def fill_uniform(out, seed: int, lo: float = -1.0, hi: float = 1.0, stream=None)
 
 
 class Batch:
-    """Many uploaded meshes assembled by one persistent launch (nsa_batch_*). Keeps references to
+    """Many uploaded meshes assembled by one launch (nsa_batch_*). Keeps references to
     the meshes, its device workspace and the last inputs so that nothing it points at is freed.
 
     Batch(meshes, ...) fixes its members; Batch.reserve(max_meshes, max_tiles, ...) makes an empty

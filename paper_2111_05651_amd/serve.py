@@ -13,10 +13,10 @@ dt. One scheduler loop moves each request through
               calls the device allocator and the budget holds by construction. A request larger than
               the whole arena is rejected at once.
   launch      whenever one of the `slots` (a stream with a reusable batch) is free, every admitted
-              request not yet running, up to a per-launch cap, goes into one persistent batched
+              request not yet running, up to a per-launch cap, goes into one batched
               launch on that stream. Requests that arrive while earlier launches run are admitted as
               memory frees up and go into the next free slot, so launches of different slots overlap
-              on the device (the tail of one persistent grid runs beside the head of the next).
+              on the device (the tail of one launch runs beside the head of the next).
   completion  an event recorded after each launch is polled; when it has fired, the launch's
               requests are stamped (latency = arrival to results ready), their budget is returned
               (or kept until release() when the caller keeps the results) and waiters wake.
@@ -24,7 +24,7 @@ dt. One scheduler loop moves each request through
               and reports them; the slot and the memory stay held until the device is done with
               them, since the kernel may still write there.
 
-The device work is that of the batched form: one launch of the library's persistent tiled kernel
+The device work is that of the batched form: one launch of the library's tiled kernel
 over the tiles of every mesh in the launch. The scheduler itself is device-agnostic (an executor
 does the launches), so its admission, batching and timeout logic also runs on the CPU.
 """
@@ -465,7 +465,7 @@ class GpuExecutor:
 
     def __init__(self, meshes, scatter: int = nsa.ATOMIC, precision: int = nsa.MIXED, slots: int = 3,
                  mode: str = "batched", device="cuda", tile_blocks: int | None = None, block_threads: int = 0,
-                 grid_wgs: int = 0, max_launch_meshes: int = 256, max_launch_tiles: int = 1 << 20, trace: bool = False,
+                 max_launch_meshes: int = 256, max_launch_tiles: int = 1 << 20, trace: bool = False,
                  resident=None, log=None):
         import torch
         if mode not in ("batched", "plain"):
@@ -474,7 +474,7 @@ class GpuExecutor:
             slots, max_launch_meshes = 1, 1
         self.mode = mode
         self.scatter, self.precision = int(scatter), int(precision)
-        self.block_threads, self.grid_wgs = int(block_threads), int(grid_wgs)
+        self.block_threads = int(block_threads)
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
@@ -590,7 +590,7 @@ class GpuExecutor:
                 if self.trace:
                     t_start = torch.cuda.Event(enable_timing=True)
                     t_start.record(s)
-                b.assemble(self.precision, grid_wgs=self.grid_wgs, block_threads=self.block_threads, stream=s)
+                b.assemble(self.precision, block_threads=self.block_threads, stream=s)
             else:
                 r = reqs[0]
                 if self.trace:

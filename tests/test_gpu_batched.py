@@ -1,4 +1,4 @@
-"""GPU tests of the batched persistent form: each mesh's result in the batch equals its solo result
+"""GPU tests of the batched form: each mesh's result in the batch equals its solo result
 (bitwise in the colour mode), matches the oracle, and a captured HIP graph replays correctly with
 new inputs installed between replays."""
 import sys
@@ -40,8 +40,10 @@ def test_batch_equals_solo_and_oracle(scatter, precision):
     vels = [torch.from_numpy(m.velocity).cuda() for m in ms]
     outs = b.alloc_outputs()
     b.set_inputs(vels, [m.rho for m in ms], [m.mu for m in ms], [m.dt for m in ms], outs)
-    for grid in (0, 8, 24):
-        b.assemble(precision, grid_wgs=grid)
+    with pytest.raises(nsa.NsaError):
+        b.assemble(precision, grid_wgs=8)  # one workgroup per tile: no grid choice
+    for rep in range(2):
+        b.assemble(precision)
         torch.cuda.synchronize()
         for m, mesh, vel, (v, r) in zip(ms, meshes, vels, outs):
             sv, sr = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=precision, scatter=scatter,
