@@ -222,21 +222,21 @@ def run_batch(args):
     log(f"batch of {len(ms_)} meshes, {nelem} tets ({time.perf_counter() - t0:.1f} s)")
     tuned = autotune.tune_batch(ms_, scat, prec, cache=None, log=log,
                                 tile_candidates=(384, 512) if scat == nsa.ATOMIC else (192, 256))
-    log(f"autotuned: {({k: tuned[k] for k in ('tile_blocks', 'block_threads', 'ms')})}")
+    log(f"autotuned: {({k: tuned[k] for k in ('tile_blocks', 'block_threads', 'grid_wgs', 'ms')})}")
     handles, b, vels, outs = autotune.build_batch(ms_, tuned["tile_blocks"], scat)
     nt = tuned["block_threads"] if scat == nsa.ATOMIC else 0
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
-        b.assemble(prec, block_threads=nt)
+        b.assemble(prec, grid_wgs=tuned["grid_wgs"], block_threads=nt)
     torch.cuda.current_stream().wait_stream(stream)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        b.assemble(prec, block_threads=nt)
+        b.assemble(prec, grid_wgs=tuned["grid_wgs"], block_threads=nt)
     cur = torch.cuda.current_stream()
     ms, per, wall = time_steps(graph.replay, args.steps, args.warmup, cur)
-    ms_direct, _, _ = time_steps(lambda: b.assemble(prec, block_threads=nt),
+    ms_direct, _, _ = time_steps(lambda: b.assemble(prec, grid_wgs=tuned["grid_wgs"], block_threads=nt),
                                  args.steps, args.warmup, cur)
     log(f"batched: graph replay {ms:.4f} ms, direct launch {ms_direct:.4f} ms")
 
@@ -256,7 +256,7 @@ def run_batch(args):
         "config": {"workload": "batch64: 64 jittered permuted cubes, n ~ U{8..48}, per-mesh rho/mu/dt",
                    "nelem": nelem, "nmesh": len(ms_), "precision": args.precision, "scatter": args.scatter,
                    "kernel": "tiled, one launch over all meshes, hipGraph-captured", "tile_blocks": tuned["tile_blocks"],
-                   "block_threads": tuned["block_threads"]},
+                   "block_threads": tuned["block_threads"], "grid_wgs": tuned["grid_wgs"]},
         "hbm_GBs": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_tiled_batch",

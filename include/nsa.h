@@ -236,8 +236,8 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
 typedef struct nsa_batch nsa_batch; /* opaque */
 
 /* Many uploaded meshes (uneven sizes) assembled by one launch of the tiled kernel over the
- * concatenated tile lists of all meshes (each mesh's tiles contiguous, one workgroup per tile, every
- * XCD a contiguous slice). Every mesh must be uploaded on the current device and
+ * concatenated tile lists of all meshes (each mesh's tiles contiguous, every XCD a contiguous slice;
+ * one workgroup per tile or a persistent grid, see nsa_assemble_batched). Every mesh must be uploaded on the current device and
  * have a tile plan for `scatter` (NSA_EUNSUPPORTED otherwise). The meshes must outlive the batch. */
 nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out);
 nsa_status nsa_batch_destroy(nsa_batch *b);
@@ -267,10 +267,11 @@ nsa_status nsa_batch_upload(nsa_batch *b, void *ws, size_t ws_bytes, void *strea
 nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const double *rho, const double *mu,
                                 const double *dt, double *const *values, double *const *rhs, int32_t accumulate,
                                 void *stream);
-/* One launch over every tile of every mesh of the batch, one workgroup per (mesh, tile).
- * opt->scatter must equal the batch's mode; opt->kernel must not be NSA_KERNEL_DIRECT;
- * opt->block_threads may pick 128 or 256 threads per workgroup in the atomic mode. grid_wgs must be
- * 0 (NSA_EINVAL otherwise; the argument is kept for a grid choice).
+/* One launch over every tile of every mesh of the batch. opt->scatter must equal the batch's mode;
+ * opt->kernel must not be NSA_KERNEL_DIRECT; opt->block_threads may pick 128 or 256 threads per
+ * workgroup in the atomic mode. grid_wgs = 0: one workgroup per (mesh, tile); grid_wgs > 0: a
+ * persistent grid of that many workgroups (rounded down to a multiple of 8, at least 8) walking the
+ * tiles, or one workgroup per tile if that is not fewer; NSA_EINVAL if negative.
  * No allocation, no memset, no host synchronisation: the call may be captured in a HIP graph, and a
  * captured graph replays with whatever inputs the last nsa_batch_set_inputs installed. */
 nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream);

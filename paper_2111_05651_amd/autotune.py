@@ -1,5 +1,6 @@
-"""Autotuner for the tiled kernel: picks the tile size (blocks per LDS tile) and the workgroup size
-for a batch of meshes by timing the candidates on the device.
+"""Autotuner for the tiled kernel: picks the tile size (blocks per LDS tile), the workgroup size and
+the grid (one workgroup per tile, or a persistent grid of a few workgroups per CU) for a batch of
+meshes by timing the candidates on the device.
 
 Every candidate runs the library's own kernel through the C-ABI on the real inputs; the search
 rebuilds the tile plans once per tile size (host work) and times launch parameters on each. The
@@ -59,9 +60,11 @@ def build_batch(meshes, tile_blocks, scatter, device="cuda"):
 
 
 def tune_batch(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, tile_candidates=(384, 512),
-               thread_candidates=(128, 256), reps=5, cache: str | None = DEFAULT_CACHE, log=None) -> dict:
-    """Best (tile_blocks, block_threads) for this batch; cached by signature(). The launch takes one
-    workgroup per tile, so grid_wgs is always 0."""
+               thread_candidates=(128, 256), grid_per_cu=(0, 1, 2), reps=5, cache: str | None = DEFAULT_CACHE,
+               log=None) -> dict:
+    """Best (tile_blocks, block_threads, grid_wgs) for this batch; cached by signature(). A grid
+    candidate g > 0 is a persistent grid of g workgroups per CU (4 g for the one-wavefront plan);
+    g = 0 is one workgroup per tile (grid_wgs 0)."""
     import torch
     key = signature(meshes, scatter, precision)
     if cache and os.path.exists(cache):
@@ -72,6 +75,7 @@ def tune_batch(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, tile_candidates=
                 return dict(hit, cached=True)
         except (OSError, ValueError):
             pass
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
     threads = thread_candidates if scatter == nsa.ATOMIC else (64,)
     trials = []
     for tb in tile_candidates:
@@ -79,10 +83,13 @@ def tune_batch(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, tile_candidates=
         handles, b, vels, outs = build_batch(meshes, tb, scatter)
         plan_s = time.perf_counter() - t0
         for nt in threads:
-            ms = _time(lambda: b.assemble(precision, block_threads=nt if nt != 64 else 0), reps)
-            trials.append(dict(tile_blocks=tb, block_threads=nt, grid_wgs=0, ms=ms))
-            if log:
-                log(f"autotune tile={tb} threads={nt}: {ms:.4f} ms (plan {plan_s:.1f} s)")
+            for g in grid_per_cu:
+                grid = g * ncu * (4 if nt == 64 else 1)
+                ms = _time(lambda: b.assemble(precision, grid_wgs=grid, block_threads=nt if nt != 64 else 0), reps)
+                trials.append(dict(tile_blocks=tb, block_threads=nt, grid_wgs=grid, ms=ms))
+                if log:
+                    log(f"autotune tile={tb} threads={nt} grid={grid or 'one per tile'}: {ms:.4f} ms "
+                        f"(plan {plan_s:.1f} s)")
         del handles, b, vels, outs
         torch.cuda.empty_cache()
     best = min(trials, key=lambda t: t["ms"])

@@ -1693,7 +1693,7 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     for (int r : o.reserved)
         if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
     const int64_t total = b->ntiles;
-    if (grid_wgs != 0) return fail(NSA_EINVAL, "grid_wgs must be 0 (one workgroup per work item)");
+    if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
     int dev = -1;
     nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st) return st;
@@ -1705,7 +1705,7 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     st = hip_check(nsa::launch_tiled_batch(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64,
                                            (const nsa::TileArgs *)(b->ws + b->r_desc.off),
                                            (const int2 *)(b->ws + b->r_work.off), total, threads, b->lds,
-                                           (hipStream_t)stream),
+                                           grid_wgs, (hipStream_t)stream),
                    "assemble (batched)");
     return st ? st : ok();
 }

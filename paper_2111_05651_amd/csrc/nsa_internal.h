@@ -87,10 +87,11 @@ __host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows
 enum class TileKern { F64, Mixed };
 size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);
-// Batched form: desc[mesh] in device memory, work[t] = (mesh, local tile); one workgroup per item.
+// Batched form: desc[mesh] in device memory, work[t] = (mesh, local tile). grid_wgs 0: one workgroup
+// per item; otherwise a persistent grid of that many workgroups (a multiple of 8, fewer than the items).
 hipError_t prepare_batch(int threads, size_t lds);
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
-                              int64_t lds, hipStream_t s);
+                              int64_t lds, int grid_wgs, hipStream_t s);
 
 hipError_t ensure_lds(const void *kern, size_t bytes);
 

@@ -549,10 +549,12 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
 }
 
 // Batched form: one launch over the tiles of many meshes. work[t] = (mesh, tile of that mesh) with
-// each mesh's tiles contiguous; desc[mesh] holds that mesh's arrays, outputs and parameters. One
-// workgroup per work item, XCD-aware as in k_tiled: workgroup w runs on XCD w % 8, and XCD x takes the
-// contiguous slice [x*per, (x+1)*per) of the work table. (A persistent grid walking the table was
-// slower: the loop kept more of the tile body's state live and the FP64 form spilled.)
+// each mesh's tiles contiguous; desc[mesh] holds that mesh's arrays, outputs and parameters. XCD-aware
+// as in k_tiled: workgroup w runs on XCD w % 8, and XCD x takes the contiguous slice
+// [x*per, (x+1)*per) of the work table. Two grids: one workgroup per work item, or (PERSIST) a
+// persistent grid whose workgroups walk every (G/8)-th item of their XCD's slice. The persistent loop
+// keeps more of the tile body's state live (the FP64 form spills more), so which is faster depends on
+// the batch; the autotuner times both.
 // A member's arguments as wavefront-uniform values: every lane loads the same words, and
 // readfirstlane keeps them in scalar registers for the whole tile (a plain copy would hold them in
 // vector registers, which the FP64 element code needs).
@@ -568,16 +570,28 @@ __device__ __forceinline__ TileArgs uniform_args(const TileArgs *p) {
     return a;
 }
 
-template <typename R, int NT>
+template <typename R, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restrict__ desc, const int2 *__restrict__ work,
                                                       int64_t total) {
     extern __shared__ double smem[];
     const int64_t per = (total + 7) / 8;
-    const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (t >= total) return;
-    const int2 w = make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
-    const TileArgs A = uniform_args(desc + w.x);
-    run_tile<R, NT>(A, w.y, smem);
+    const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
+    if (PERSIST) {
+        const int64_t nslot = gridDim.x >> 3;
+        const int64_t hi = lo + per < total ? lo + per : total;
+        for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nslot) {
+            const int2 w =
+                make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
+            const TileArgs A = uniform_args(desc + w.x);
+            run_tile<R, NT>(A, w.y, smem);
+        }
+    } else {
+        const int64_t t = lo + (blockIdx.x >> 3);
+        if (t >= total) return;
+        const int2 w = make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
+        const TileArgs A = uniform_args(desc + w.x);
+        run_tile<R, NT>(A, w.y, smem);
+    }
 }
 
 // ================================================================================================
@@ -751,32 +765,47 @@ hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s) {
 
 hipError_t prepare_batch(int threads, size_t lds) {
     hipError_t e = hipSuccess;
-    for (const void *k : {reinterpret_cast<const void *>(k_tiled_batch<double, 64>),
-                          reinterpret_cast<const void *>(k_tiled_batch<float, 64>),
-                          reinterpret_cast<const void *>(k_tiled_batch<double, 128>),
-                          reinterpret_cast<const void *>(k_tiled_batch<float, 128>),
-                          reinterpret_cast<const void *>(k_tiled_batch<double, 256>),
-                          reinterpret_cast<const void *>(k_tiled_batch<float, 256>)})
+    for (const void *k : {reinterpret_cast<const void *>(k_tiled_batch<double, 64, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 64, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 128, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 128, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 256, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 256, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 64, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 64, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 128, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 128, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 256, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 256, true>)})
         if (e == hipSuccess) e = ensure_lds(k, lds);
     (void)threads;
     return e;
 }
 
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
-                              int64_t lds, hipStream_t s) {
+                              int64_t lds, int grid_wgs, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     const int nt = (threads == 64 || threads == 128) ? threads : 256;
-    const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(nt);
+    const int64_t items = 8 * ((total + 7) / 8);
+    const bool persist = grid_wgs > 0 && grid_wgs < items;
+    const dim3 grid((unsigned)(persist ? std::max(8, grid_wgs & ~7) : items)), block(nt);
     const bool mixed = k == TileKern::Mixed;
-#define NSA_LAUNCH_BATCH(T, N) \
-    hipLaunchKernelGGL((k_tiled_batch<T, N>), grid, block, (size_t)lds, s, desc, work, total)
-    if (nt == 64) {
-        if (mixed) NSA_LAUNCH_BATCH(float, 64); else NSA_LAUNCH_BATCH(double, 64);
-    } else if (nt == 128) {
-        if (mixed) NSA_LAUNCH_BATCH(float, 128); else NSA_LAUNCH_BATCH(double, 128);
-    } else {
-        if (mixed) NSA_LAUNCH_BATCH(float, 256); else NSA_LAUNCH_BATCH(double, 256);
+#define NSA_LAUNCH_BATCH(T, N, P) \
+    hipLaunchKernelGGL((k_tiled_batch<T, N, P>), grid, block, (size_t)lds, s, desc, work, total)
+#define NSA_LAUNCH_BATCH_NT(P)                                                                  \
+    if (nt == 64) {                                                                             \
+        if (mixed) NSA_LAUNCH_BATCH(float, 64, P); else NSA_LAUNCH_BATCH(double, 64, P);       \
+    } else if (nt == 128) {                                                                     \
+        if (mixed) NSA_LAUNCH_BATCH(float, 128, P); else NSA_LAUNCH_BATCH(double, 128, P);     \
+    } else {                                                                                    \
+        if (mixed) NSA_LAUNCH_BATCH(float, 256, P); else NSA_LAUNCH_BATCH(double, 256, P);     \
     }
+    if (persist) {
+        NSA_LAUNCH_BATCH_NT(true)
+    } else {
+        NSA_LAUNCH_BATCH_NT(false)
+    }
+#undef NSA_LAUNCH_BATCH_NT
 #undef NSA_LAUNCH_BATCH
     return hipGetLastError();
 }

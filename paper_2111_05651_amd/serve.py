@@ -465,7 +465,7 @@ class GpuExecutor:
 
     def __init__(self, meshes, scatter: int = nsa.ATOMIC, precision: int = nsa.MIXED, slots: int = 3,
                  mode: str = "batched", device="cuda", tile_blocks: int | None = None, block_threads: int = 0,
-                 max_launch_meshes: int = 256, max_launch_tiles: int = 1 << 20, trace: bool = False,
+                 grid_wgs: int = 0, max_launch_meshes: int = 256, max_launch_tiles: int = 1 << 20, trace: bool = False,
                  resident=None, log=None):
         import torch
         if mode not in ("batched", "plain"):
@@ -474,7 +474,7 @@ class GpuExecutor:
             slots, max_launch_meshes = 1, 1
         self.mode = mode
         self.scatter, self.precision = int(scatter), int(precision)
-        self.block_threads = int(block_threads)
+        self.block_threads, self.grid_wgs = int(block_threads), int(grid_wgs)
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
@@ -590,7 +590,7 @@ class GpuExecutor:
                 if self.trace:
                     t_start = torch.cuda.Event(enable_timing=True)
                     t_start.record(s)
-                b.assemble(self.precision, block_threads=self.block_threads, stream=s)
+                b.assemble(self.precision, grid_wgs=self.grid_wgs, block_threads=self.block_threads, stream=s)
             else:
                 r = reqs[0]
                 if self.trace:

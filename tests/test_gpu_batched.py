@@ -41,9 +41,10 @@ def test_batch_equals_solo_and_oracle(scatter, precision):
     outs = b.alloc_outputs()
     b.set_inputs(vels, [m.rho for m in ms], [m.mu for m in ms], [m.dt for m in ms], outs)
     with pytest.raises(nsa.NsaError):
-        b.assemble(precision, grid_wgs=8)  # one workgroup per tile: no grid choice
-    for rep in range(2):
-        b.assemble(precision)
+        b.assemble(precision, grid_wgs=-8)
+    # one workgroup per tile, and persistent grids smaller than the tile count
+    for grid in (0, 8, 24):
+        b.assemble(precision, grid_wgs=grid)
         torch.cuda.synchronize()
         for m, mesh, vel, (v, r) in zip(ms, meshes, vels, outs):
             sv, sr = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=precision, scatter=scatter,
