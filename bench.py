@@ -221,7 +221,7 @@ def run_batch(args):
     nelem = sum(m.nelem for m in ms_)
     log(f"batch of {len(ms_)} meshes, {nelem} tets ({time.perf_counter() - t0:.1f} s)")
     tuned = autotune.tune_batch(ms_, scat, prec, cache=None, log=log,
-                                tile_candidates=(384, 512) if scat == nsa.ATOMIC else (192, 256))
+                                tile_candidates=(384, 512) if scat == nsa.ATOMIC else (160, 256))
     log(f"autotuned: {({k: tuned[k] for k in ('tile_blocks', 'block_threads', 'grid_wgs', 'ms')})}")
     handles, b, vels, outs = autotune.build_batch(ms_, tuned["tile_blocks"], scat)
     nt = tuned["block_threads"] if scat == nsa.ATOMIC else 0
@@ -287,7 +287,7 @@ def run_serve(args):
     t0 = time.perf_counter()
     c4 = inputs.config_batch()
     hs = [nsa.Mesh.from_inputs(m, tile_blocks=512 if scat == nsa.ATOMIC else 0,
-                               tile_blocks_colour=0 if scat == nsa.ATOMIC else 256).upload() for m in c4]
+                               tile_blocks_colour=0 if scat == nsa.ATOMIC else 160).upload() for m in c4]
     b = nsa.Batch(hs, scat)
     vels = [torch.from_numpy(m.velocity).cuda() for m in c4]
     outs = b.alloc_outputs()
@@ -422,7 +422,7 @@ def main():
     ap.add_argument("--tile-rows-residual", type=int, default=256, help="rows per tile of the residual plan")
     ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
-    ap.add_argument("--tile-blocks-colour", type=int, default=256, help="tile size of the colour-mode plan")
+    ap.add_argument("--tile-blocks-colour", type=int, default=160, help="tile size of the colour-mode plan")
     ap.add_argument("--no-beside", action="store_true",
                     help="skip timing the other precision beside (mixed beside FP64, or FP64 beside mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

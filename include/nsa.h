@@ -159,7 +159,7 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
  * block rows whose LDS footprint (136 bytes per block, 44 per row, 48 per touched node) stays within
  * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB). A tile's elements are
  * every element with a node in it, coloured so that elements of one tile colour share no owned
- * node. Defaults: 512 (NSA_ATOMIC, 256-thread workgroups) and 256 (NSA_COLOUR, one wavefront per
+ * node. Defaults: 512 (NSA_ATOMIC, 256-thread workgroups) and 160 (NSA_COLOUR, one wavefront per
  * tile); tile_blocks = 0 drops the plan of that mode (the tiled kernel then refuses the mode and
  * NSA_KERNEL_AUTO falls back to the direct kernel). Plans are built on first need
  * (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be called before nsa_mesh_upload
