@@ -236,10 +236,10 @@ int parallel_chunks(int64_t n, F f) {
 // the LDS serves together: 16 lanes over 32 four-byte banks) chosen so that, for each owned-row
 // iteration k and column b, the blocks the lanes add into sit on different bank pairs (value i of
 // block slot s of the tile lies on bank pair (17 s + i) mod 16) and in different rows (same row:
-// same diagonal block, same address). Each record may take its owned
-// rows in any order and its other vertices in any order; the chosen vertex order is written back to
-// vord. Records stay grouped by owned-row count; each half-wavefront slot takes, among the next few
-// records of the group, the one (and vertex order) that adds the least to the lanes already placed.
+// same diagonal block, same address). Each record may take its owned rows in any order and its
+// other vertices in any order; the chosen vertex order is written back to vord. Records stay grouped
+// by owned-row count; each slot of a group takes, among the next 8 records of the count, the one (and
+// vertex order) that adds the least to the lanes already placed in the group.
 // by_row: the adds of owned-row iteration k go to per-row accumulators (the residual tiles: double
 // 5 r + c of the tile's accumulators, bank pair (5 r + c) mod 16), so the bank pair of a lane follows
 // its row alone and only the order of the owned rows matters.
