@@ -413,7 +413,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8", "batch64", "serve"])
-    ap.add_argument("--precision", default="fp64", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default=None, choices=["mixed", "fp64"],
+                    help="default: fp64 for the single-mesh workloads (mixed timed beside), mixed for batch64 "
+                         "and serve (compared against plain FP64 launches)")
     ap.add_argument("--scatter", default="atomic", choices=["atomic", "colour"])
     ap.add_argument("--kernel", default="tiled", choices=["tiled", "direct", "auto", "gather"])
     ap.add_argument("--tile-blocks-gather", type=int, default=512, help="blocks per tile of the gather plan")
@@ -438,6 +440,8 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="instead: time a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = "mixed" if args.workload in ("batch64", "serve") else "fp64"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
               "documented but not built", file=sys.stderr)
