@@ -906,7 +906,7 @@ const char *nsa_status_string(nsa_status st) {
 
 const char *nsa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t nsa_version(void) { return 200; }
+int32_t nsa_version(void) { return 201; }
 
 nsa_status nsa_pattern_count(int64_t npoin, int64_t nelem, const int32_t *lnods, int64_t *bptr,
                              int64_t *nnzb) {
