@@ -127,8 +127,8 @@ const char *nsa_status_string(nsa_status st);
 /* Detail of the last failure on this thread ("" if none). Valid until the next libnsa call on the
  * same thread. */
 const char *nsa_last_error(void);
-/* Library version as major*10000 + minor*100 + patch (2.01: nsa_assemble_batched takes grid_wgs 0
- * as one workgroup per tile). */
+/* Library version as major*10000 + minor*100 + patch (201 = 0.2.1: nsa_assemble_batched takes
+ * grid_wgs 0 as one workgroup per tile). */
 int32_t nsa_version(void);
 
 /* ---- block pattern of the node graph (host, standalone) ------------------------------------- */
