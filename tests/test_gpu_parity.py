@@ -203,6 +203,49 @@ def test_cube128_sampled(precision):
         say(f"[parity] cube128 sampled errors {err}")
 
 
+def device_class_errors(v, ref_v, r, ref_r):
+    """The parity metric of tests/parity.py (per class max |got - ref| / max |ref|) on device tensors."""
+    v, ref_v, r, ref_r = v.view(-1, 4, 4), ref_v.view(-1, 4, 4), r.view(-1, 4), ref_r.view(-1, 4)
+    out = {}
+    for k, (a, b) in {"uu": (slice(0, 3), slice(0, 3)), "up": (slice(0, 3), slice(3, 4)),
+                      "pu": (slice(3, 4), slice(0, 3)), "pp": (slice(3, 4), slice(3, 4))}.items():
+        out[k] = float((v[:, a, b] - ref_v[:, a, b]).abs().max() / ref_v[:, a, b].abs().max())
+    for k, sel in (("rhs_u", slice(0, 3)), ("rhs_p", slice(3, 4))):
+        out[k] = float((r[:, sel] - ref_r[:, sel]).abs().max() / ref_r[:, sel].abs().max())
+    return out
+
+
+def test_cube128_whole_mesh_consistency():
+    """Every entry of the 128^3 result (509M values), beyond the sampled rows the oracle computes: the
+    benchmark's launch (tiled, atomic, FP64), the tiled deterministic plan and the direct kernel
+    with its global colour classes agree to the FP64 bar everywhere; the mixed form stays within its
+    bar everywhere; the deterministic plan repeats bit for bit."""
+    m = inputs.config_128()
+    say(f"[parity] cube128 whole mesh nelem={m.nelem}")
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512).upload()
+    vel = torch.from_numpy(m.velocity).cuda()
+
+    def run(precision, scatter, kernel):
+        out = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=precision, scatter=scatter, kernel=kernel)
+        torch.cuda.synchronize()
+        return out
+
+    ref_v, ref_r = run(nsa.FP64, nsa.ATOMIC, nsa.KERNEL_TILED)
+    for name, (prec, scat, kern), tol in (("tiled deterministic", (nsa.FP64, nsa.COLOUR, nsa.KERNEL_TILED), TOL_FP64),
+                                          ("direct colour classes", (nsa.FP64, nsa.COLOUR, nsa.KERNEL_DIRECT), TOL_FP64),
+                                          ("mixed", (nsa.MIXED, nsa.ATOMIC, nsa.KERNEL_TILED), TOL_MIXED)):
+        v, r = run(prec, scat, kern)
+        err = device_class_errors(v, ref_v, r, ref_r)
+        say(f"[parity] cube128 whole mesh {name}: {err}")
+        assert max(err.values()) <= tol, (name, err)
+        if name == "tiled deterministic":
+            v2, r2 = run(prec, scat, kern)
+            assert torch.equal(v, v2) and torch.equal(r, r2), "deterministic plan: bitwise repeat"
+            del v2, r2
+        del v, r
+        torch.cuda.empty_cache()
+
+
 def test_gather_bitwise_independent_of_tiling_and_mode():
     """Each block is summed in element order whatever the tile size, the workgroup size or the
     scatter mode: all of them give the same bits."""
