@@ -116,6 +116,22 @@ def _ptr(a) -> int:
     return a.data_ptr()
 
 
+def _dev_tensor(t, shape, name: str, device=None):
+    """The C entry points take bare pointers, so the binding checks what only it can see: a contiguous
+    float64 device tensor of exactly the expected shape (on the mesh's device when one is given)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor (got {t.dtype}, {t.device}, "
+                         f"contiguous={t.is_contiguous()})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the mesh on {device}")
+    return t.data_ptr()
+
+
 def _stream_handle(stream) -> int | None:
     if stream is None:
         import torch
@@ -301,11 +317,17 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
              accumulate=False, block_threads=0, kernel=KERNEL_AUTO, values=None, rhs=None, stream=None):
     """Launch nsa_assemble on the stream (default: torch's current stream); returns (values, rhs)
     as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given)."""
+    if mesh.ws is None:
+        raise ValueError("the mesh has not been uploaded (Mesh.upload)")
+    dev = mesh.ws.device
     if values is None or rhs is None:
-        values, rhs = mesh.alloc_outputs(vel.device)
+        values, rhs = mesh.alloc_outputs(dev)
+    pv = _dev_tensor(vel, (mesh.npoin, 3), "vel", dev)
+    pval = _dev_tensor(values, (mesh.nnzb, 4, 4), "values", dev)
+    prhs = _dev_tensor(rhs, (mesh.npoin, 4), "rhs", dev)
     o = make_options(precision, scatter, accumulate, block_threads, kernel)
-    _check(load().nsa_assemble(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o), _ptr(values),
-                               _ptr(rhs), _stream_handle(stream)), "nsa_assemble")
+    _check(load().nsa_assemble(mesh._h, pv, float(rho), float(mu), float(dt), C.byref(o), pval, prhs,
+                               _stream_handle(stream)), "nsa_assemble")
     return values, rhs
 
 
@@ -314,17 +336,20 @@ def assemble_residual(mesh: Mesh, vel, rho, mu, dt, precision=FP64, accumulate=F
     """Explicit-residual outputs (rhsid [npoin][3], dt_rho [npoin], mass_rho [npoin]) on the device;
     outputs are allocated when not given."""
     import torch
-    dev = vel.device if hasattr(vel, "device") else "cuda"
+    if mesh.ws is None:
+        raise ValueError("the mesh has not been uploaded (Mesh.upload)")
+    dev = mesh.ws.device
     if rhsid is None:
         rhsid = torch.empty((mesh.npoin, 3), dtype=torch.float64, device=dev)
     if dt_rho is None:
         dt_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
     if mass_rho is None:
         mass_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
+    ptrs = (_dev_tensor(vel, (mesh.npoin, 3), "vel", dev), _dev_tensor(rhsid, (mesh.npoin, 3), "rhsid", dev),
+            _dev_tensor(dt_rho, (mesh.npoin,), "dt_rho", dev), _dev_tensor(mass_rho, (mesh.npoin,), "mass_rho", dev))
     o = make_options(precision, ATOMIC, accumulate)
-    _check(load().nsa_assemble_residual(mesh._h, _ptr(vel), float(rho), float(mu), float(dt), C.byref(o),
-                                        _ptr(rhsid), _ptr(dt_rho), _ptr(mass_rho), _stream_handle(stream)),
-           "nsa_assemble_residual")
+    _check(load().nsa_assemble_residual(mesh._h, ptrs[0], float(rho), float(mu), float(dt), C.byref(o), *ptrs[1:],
+                                        _stream_handle(stream)), "nsa_assemble_residual")
     return rhsid, dt_rho, mass_rho
 
 
@@ -389,16 +414,22 @@ class Batch:
     def set_inputs(self, vels, rho, mu, dt, outputs, accumulate=False, stream=None):
         """vels: device tensors [npoin][3]; rho, mu, dt: sequences; outputs: [(values, rhs), ...]."""
         n = len(self.meshes)
+        vels, outputs = list(vels), list(outputs)
+        if not (len(vels) == len(outputs) == len(rho) == len(mu) == len(dt) == n):
+            raise ValueError(f"set_inputs: expected {n} velocities, outputs and parameters each")
+        dev = self.ws.device
         P = C.c_void_p
-        v = (P * n)(*[x.data_ptr() for x in vels])
-        va = (P * n)(*[o[0].data_ptr() for o in outputs])
-        ra = (P * n)(*[o[1].data_ptr() for o in outputs])
+        v = (P * n)(*[_dev_tensor(x, (m.npoin, 3), f"vels[{i}]", dev) for i, (x, m) in enumerate(zip(vels, self.meshes))])
+        va = (P * n)(*[_dev_tensor(o[0], (m.nnzb, 4, 4), f"outputs[{i}][0]", dev)
+                       for i, (o, m) in enumerate(zip(outputs, self.meshes))])
+        ra = (P * n)(*[_dev_tensor(o[1], (m.npoin, 4), f"outputs[{i}][1]", dev)
+                       for i, (o, m) in enumerate(zip(outputs, self.meshes))])
         dr = (C.c_double * n)(*[float(x) for x in rho])
         dm = (C.c_double * n)(*[float(x) for x in mu])
         dd = (C.c_double * n)(*[float(x) for x in dt])
         _check(load().nsa_batch_set_inputs(self._h, v, dr, dm, dd, va, ra, int(bool(accumulate)),
                                            _stream_handle(stream)), "nsa_batch_set_inputs")
-        self._keep = (list(vels), list(outputs))
+        self._keep = (vels, outputs)
 
     def assemble(self, precision=MIXED, grid_wgs=0, block_threads=0, stream=None):
         o = make_options(precision, self.scatter, block_threads=block_threads)

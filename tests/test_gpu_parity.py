@@ -142,6 +142,30 @@ def test_colour_path_reproducible_under_load():
         assert np.array_equal(v.cpu().numpy(), v0) and np.array_equal(r.cpu().numpy(), r0), f"run {it}"
 
 
+def test_binding_rejects_bad_tensors():
+    """The C entry points take bare pointers; the binding refuses tensors that would make a kernel
+    read or write outside them, before any launch."""
+    m = inputs.make_mesh(2, jitter=True, seed=3)
+    mesh = nsa.Mesh.from_inputs(m).upload()
+    vel = torch.from_numpy(m.velocity).cuda()
+    values, rhs = mesh.alloc_outputs()
+    bad_vel = [vel.float(), vel[:-1], vel.t().contiguous(), vel.t(), vel.cpu()]
+    for v in bad_vel:
+        with pytest.raises(ValueError):
+            nsa.assemble(mesh, v, m.rho, m.mu, m.dt, values=values, rhs=rhs)
+    with pytest.raises(ValueError):
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, values=values[:-1], rhs=rhs)
+    with pytest.raises(ValueError):
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, values=values, rhs=rhs.t())
+    with pytest.raises(ValueError):
+        nsa.assemble_residual(mesh, vel, m.rho, m.mu, m.dt, rhsid=torch.empty((m.npoin, 3), device="cuda"))
+    # the well-formed call still works after the refusals
+    v, r = nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, values=values, rhs=rhs)
+    torch.cuda.synchronize()
+    ref_v, ref_r = oracle.assemble(m)
+    assert_parity(v.cpu().numpy(), ref_v, r.cpu().numpy(), ref_r, TOL_FP64, "after refusals")
+
+
 def test_empty_and_tiny():
     mesh = nsa.Mesh(np.zeros((0, 4), np.int32), np.zeros((3, 3))).upload()
     vel = torch.zeros((3, 3), dtype=torch.float64, device="cuda")

@@ -96,6 +96,25 @@ def test_status_codes(lib):
     assert lib.nsa_mesh_release_host(mesh._h) == nsa.NSA_ESTATE
 
 
+def test_binding_checks_tensors_before_any_call(lib):
+    """The binding refuses what the bare-pointer ABI cannot see: a mesh not uploaded, host or
+    non-float64 tensors (checked on the CPU; the device-side cases run with the GPU tests)."""
+    import torch
+    m = inputs.make_mesh(2, seed=4)
+    mesh = nsa.Mesh.from_inputs(m)
+    vel = torch.from_numpy(m.velocity)
+    with pytest.raises(ValueError, match="uploaded"):
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt)
+    with pytest.raises(ValueError, match="uploaded"):
+        nsa.assemble_residual(mesh, vel, m.rho, m.mu, m.dt)
+    with pytest.raises(ValueError, match="float64 device"):
+        nsa._dev_tensor(vel, (m.npoin, 3), "vel")
+    with pytest.raises(ValueError, match="float64 device"):
+        nsa._dev_tensor(vel.float(), (m.npoin, 3), "vel")
+    with pytest.raises(TypeError):
+        nsa._dev_tensor(m.velocity, (m.npoin, 3), "vel")
+
+
 def test_empty_mesh(lib):
     mesh = nsa.Mesh(np.zeros((0, 4), np.int32), np.zeros((5, 3)))
     assert mesh.nelem == 0 and mesh.nnzb == 0 and mesh.info.ncolours == 0
