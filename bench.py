@@ -286,8 +286,8 @@ def run_serve(args):
     # reference rate: the 64-mesh batch, one launch (default plan)
     t0 = time.perf_counter()
     c4 = inputs.config_batch()
-    hs = [nsa.Mesh.from_inputs(m, tile_blocks=512 if scat == nsa.ATOMIC else 0,
-                               tile_blocks_colour=0 if scat == nsa.ATOMIC else 160).upload() for m in c4]
+    hs = [nsa.Mesh.from_inputs(m, tile_blocks=None if scat == nsa.ATOMIC else 0,
+                               tile_blocks_colour=0 if scat == nsa.ATOMIC else None).upload() for m in c4]
     b = nsa.Batch(hs, scat)
     vels = [torch.from_numpy(m.velocity).cuda() for m in c4]
     outs = b.alloc_outputs()

@@ -19,8 +19,9 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "nsa_autotune.js
 
 
 def signature(meshes, scatter, precision) -> str:
-    """Key of a batch: sizes of its meshes, mode and precision."""
+    """Key of a batch: library version (plans change with it), sizes of its meshes, mode and precision."""
     h = hashlib.sha256()
+    h.update(f"v{nsa.load().nsa_version()};".encode())
     for m in meshes:
         h.update(f"{m.nelem}:{m.npoin};".encode())
     h.update(f"s{scatter}p{precision}".encode())

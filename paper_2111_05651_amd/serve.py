@@ -479,8 +479,8 @@ class GpuExecutor:
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.slots = int(slots)
-        # the library's default plan sizes unless given
-        tb = tile_blocks if tile_blocks is not None else (512 if self.scatter == nsa.ATOMIC else 160)
+        # the library's default plan size unless given (None leaves it to the library)
+        tb = tile_blocks
         self.meshes = list(resident) if resident is not None else []
         self.shared = resident is not None
         t0 = time.perf_counter()
