@@ -827,6 +827,8 @@ void plan_layout(nsa_mesh *m) {
         take(P.r_nptr, P.ok ? P.nptr.size() * sizeof(int64_t) : 0);
         take(P.r_nodes, P.ok ? P.nodes.size() * sizeof(int32_t) : 0);
         take(P.r_recs, P.ok ? P.recs.size() * sizeof(nsa::TileRec) : 0);
+        take(P.r_b0, P.ok ? P.row.size() * sizeof(int64_t) : 0);
+        take(P.r_npad, P.ok ? (size_t)P.ntiles() * P.cap_nodes * sizeof(int32_t) : 0);
     }
     nsa::GatherPlan &G = m->gplan;
     take(G.r_row, G.ok ? G.row.size() * sizeof(int32_t) : 0);
@@ -1210,6 +1212,22 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
             for (int64_t i = 0; i < np; i++)
                 for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
         }
+        // per plan: block offset of each tile and its node ids at a fixed stride (padding repeats
+        // the tile's first node, so every padded gather stays inside the mesh)
+        std::vector<int64_t> b0v[2];
+        std::vector<int32_t> npad[2];
+        for (int k = 0; k < 2; k++) {
+            const nsa::TilePlan &P = m->plan[k];
+            if (!P.ok) continue;
+            b0v[k].resize(P.row.size());
+            for (size_t t = 0; t < P.row.size(); t++) b0v[k][t] = m->bptr[P.row[t]];
+            const int64_t nt = P.ntiles(), cap = P.cap_nodes;
+            npad[k].resize((size_t)(nt * cap));
+            for (int64_t t = 0; t < nt; t++) {
+                const int64_t a = P.nptr[t], n = P.nptr[t + 1] - a;
+                for (int64_t i = 0; i < cap; i++) npad[k][t * cap + i] = P.nodes[a + (i < n ? i : 0)];
+            }
+        }
         char *w = (char *)ws;
         nsa_status st;
         struct Up { const nsa::Region &r; const void *src; };
@@ -1221,8 +1239,10 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
                           {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
                           {P0.r_row, P0.row.data()}, {P0.r_eptr, P0.eptr.data()}, {P0.r_nptr, P0.nptr.data()},
                           {P0.r_nodes, P0.nodes.data()}, {P0.r_recs, P0.recs.data()},
+                          {P0.r_b0, b0v[0].data()}, {P0.r_npad, npad[0].data()},
                           {P1.r_row, P1.row.data()}, {P1.r_eptr, P1.eptr.data()}, {P1.r_nptr, P1.nptr.data()},
                           {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()},
+                          {P1.r_b0, b0v[1].data()}, {P1.r_npad, npad[1].data()},
                           {G.r_row, G.row.data()}, {G.r_nptr, G.nptr.data()}, {G.r_nodes, G.nodes.data()},
                           {G.r_eptr, G.eptr.data()}, {G.r_recs, G.recs.data()}, {G.r_pptr, G.pptr.data()},
                           {G.r_pairs, G.pairs.data()}, {G.r_slots, G.slots.data()},
@@ -1357,6 +1377,9 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         t.rec = (const uint2 *)(m->ws + P.r_recs.off);
         t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
         t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
+        t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
+        t.tile_npad = (const int32_t *)(m->ws + P.r_npad.off);
+        t.cap_nodes = P.cap_nodes;
         t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
         t.coord = (const double4 *)(m->ws + m->r_coord4.off);
         t.vel = vel;
@@ -1655,6 +1678,9 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
             t.rec = (const uint2 *)(m->ws + P.r_recs.off);
             t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
             t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
+            t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
+            t.tile_npad = (const int32_t *)(m->ws + P.r_npad.off);
+            t.cap_nodes = P.cap_nodes;
             t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
             t.coord = (const double4 *)(m->ws + m->r_coord4.off);
         }

@@ -61,6 +61,11 @@ struct TileArgs {
     const uint2 *rec = nullptr;          // [sum] TileRec as 3 x uint2
     const int64_t *tile_nptr = nullptr;  // [ntiles+1]
     const int32_t *tile_nodes = nullptr; // [sum]
+    // the prologue's loads without a dependent round trip: tile_b0[t] = bptr[tile_row[t]] ([ntiles+1])
+    // and each tile's node ids at a fixed stride cap_nodes, padded with a node of the tile
+    const int64_t *tile_b0 = nullptr;
+    const int32_t *tile_npad = nullptr;  // [ntiles * cap_nodes]
+    int32_t cap_nodes = 0;
     const int64_t *bptr = nullptr;       // [npoin+1]
     const double4 *coord = nullptr;      // [npoin] (x, y, z, 0)
     const double *vel = nullptr;         // [npoin][3]
@@ -213,7 +218,7 @@ struct TilePlan {
     std::vector<int64_t> nptr;   // [ntiles+1]
     std::vector<int32_t> nodes;
     std::vector<TileRec> recs;
-    Region r_row, r_eptr, r_nptr, r_nodes, r_recs;
+    Region r_row, r_eptr, r_nptr, r_nodes, r_recs, r_b0, r_npad;
     int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
     int64_t nrec() const { return ok ? eptr.back() : 0; }
 };

@@ -471,11 +471,18 @@ __device__ __forceinline__ void tile_element(const TileArgs &A, const Rec &rc, i
 template <typename R, int NT>
 __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double *smem) {
     const int tid = threadIdx.x;
+    // The node ids sit at a fixed stride per tile, so the first pass of node gathers needs no tile
+    // header: it is issued first and waits for one round trip (ids, then coordinates and velocities)
+    // while the header loads are in flight.
+    const int32_t *nid = A.tile_npad + tile * A.cap_nodes;
+    const bool first = tid < A.cap_nodes;
+    const int64_t g1 = first ? nid[tid] : 0;
+    const double4 c1 = A.coord[g1];
+    const double u1 = A.vel[3 * g1], v1 = A.vel[3 * g1 + 1], w1 = A.vel[3 * g1 + 2];
     const int r0 = A.tile_row[tile], r1 = A.tile_row[tile + 1], nrows = r1 - r0;
-    const int64_t b0 = A.bptr[r0];
-    const int nblk = (int)(A.bptr[r1] - b0);
-    const int64_t n0 = A.tile_nptr[tile];
-    const int nnod = (int)(A.tile_nptr[tile + 1] - n0);
+    const int64_t b0 = A.tile_b0[tile];
+    const int nblk = (int)(A.tile_b0[tile + 1] - b0);
+    const int nnod = (int)(A.tile_nptr[tile + 1] - A.tile_nptr[tile]);
     // block image at a padded stride (a block's 16 values sit at immediate offsets from one base and
     // neighbouring slots start on different banks), RHS rows, node table, row offsets
     double *acc = smem;
@@ -487,8 +494,14 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     Rec cur{};
     int64_t p = p0 + tid;
     if (p < p1) cur = load_rec(A, p);
-    for (int i = tid; i < nnod; i += NT) {
-        const int64_t gnode = A.tile_nodes[n0 + i];
+    if (first && tid < nnod) {
+        double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * tid);
+        nd[0] = make_double2(c1.x, c1.y);
+        nd[1] = make_double2(c1.z, u1);
+        nd[2] = make_double2(v1, w1);
+    }
+    for (int i = tid + NT; i < nnod; i += NT) {
+        const int64_t gnode = nid[i];
         const double4 c = A.coord[gnode];
         const double *v = A.vel + 3 * gnode;
         double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
