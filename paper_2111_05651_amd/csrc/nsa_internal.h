@@ -89,6 +89,20 @@ __host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows
     return lds_nodes_off(nblk, nrows) + 6 * (int64_t)nnodes;
 }
 
+// Workgroup-to-tile order of the row-tiled kernels. Workgroup w runs on XCD w % 8; XCD x takes the
+// runs x, x + 8, x + 16, ... of kXcdRun consecutive tiles, in dispatch order. Neighbouring tiles of a
+// run share nodal data in that XCD's L2, and every XCD draws runs from the whole row range: tiles at
+// the two ends of a bandwidth-reducing order take longer, so one contiguous eighth per XCD left some
+// XCDs finishing several percent after the others. The map is one-to-one from [0, xcd_grid(n)) onto
+// [0, xcd_grid(n)) and so covers every tile below n; workgroups mapped at or beyond n return at once.
+constexpr int kXcdRun = 16;
+__host__ __device__ constexpr int64_t xcd_grid(int64_t n) {
+    return 8 * (((n + kXcdRun - 1) / kXcdRun + 7) / 8) * kXcdRun;
+}
+__host__ __device__ constexpr int64_t xcd_item(int64_t w) {
+    return (((w >> 3) / kXcdRun) * 8 + (w & 7)) * kXcdRun + (w >> 3) % kXcdRun;
+}
+
 enum class TileKern { F64, Mixed };
 size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);

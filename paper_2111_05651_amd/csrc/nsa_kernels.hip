@@ -553,19 +553,17 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
 template <typename R, int NT>
 __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     extern __shared__ double smem[];
-    // XCD-aware order: workgroup w runs on XCD w % 8, so give each XCD a contiguous run of tiles
-    // (neighbouring tiles share nodal data in that XCD's L2).
-    const int64_t per = (A.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // XCD-aware order (xcd_item): runs of consecutive tiles per XCD, drawn from the whole mesh
+    const int64_t tile = xcd_item(blockIdx.x);
     if (tile >= A.ntiles) return;
     run_tile<R, NT>(A, tile, smem);
 }
 
 // Batched form: one launch over the tiles of many meshes. work[t] = (mesh, tile of that mesh) with
 // each mesh's tiles contiguous; desc[mesh] holds that mesh's arrays, outputs and parameters. XCD-aware
-// as in k_tiled: workgroup w runs on XCD w % 8, and XCD x takes the contiguous slice
-// [x*per, (x+1)*per) of the work table. Two grids: one workgroup per work item, or (PERSIST) a
-// persistent grid whose workgroups walk every (G/8)-th item of their XCD's slice. The persistent loop
+// (workgroup w runs on XCD w % 8). Two grids: one workgroup per work item, in the order of k_tiled
+// (xcd_item), or (PERSIST) a persistent grid whose workgroups walk every (G/8)-th item of their
+// XCD's contiguous eighth [x*per, (x+1)*per) of the work table. The persistent loop
 // keeps more of the tile body's state live (the FP64 form spills more), so which is faster depends on
 // the batch; the autotuner times both.
 // A member's arguments as wavefront-uniform values: every lane loads the same words, and
@@ -587,9 +585,9 @@ template <typename R, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restrict__ desc, const int2 *__restrict__ work,
                                                       int64_t total) {
     extern __shared__ double smem[];
-    const int64_t per = (total + 7) / 8;
-    const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
     if (PERSIST) {
+        const int64_t per = (total + 7) / 8;
+        const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
         const int64_t nslot = gridDim.x >> 3;
         const int64_t hi = lo + per < total ? lo + per : total;
         for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nslot) {
@@ -599,7 +597,7 @@ __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restric
             run_tile<R, NT>(A, w.y, smem);
         }
     } else {
-        const int64_t t = lo + (blockIdx.x >> 3);
+        const int64_t t = xcd_item(blockIdx.x);
         if (t >= total) return;
         const int2 w = make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
         const TileArgs A = uniform_args(desc + w.x);
@@ -675,8 +673,7 @@ __device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, int 
 template <typename R, int NT>
 __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
     extern __shared__ double smem[];
-    const int64_t per = (A.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t tile = xcd_item(blockIdx.x);  // XCD-aware order as in k_tiled
     if (tile >= A.ntiles) return;
     const int tid = threadIdx.x;
     const int r0 = A.tile_row[tile], nrows = A.tile_row[tile + 1] - r0;
@@ -747,9 +744,8 @@ hipError_t ensure_lds(const void *kern, size_t bytes) {
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = (size_t)a.lds_bytes;
-    const int64_t per = (a.ntiles + 7) / 8;
     const int nt = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
-    const dim3 grid((unsigned)(8 * per)), block(nt);
+    const dim3 grid((unsigned)xcd_grid(a.ntiles)), block(nt);
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = ensure_lds(reinterpret_cast<const void *>(kern), lds);
         if (e != hipSuccess) return e;
@@ -765,8 +761,7 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
 hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = (size_t)a.lds_bytes;
-    const int64_t per = (a.ntiles + 7) / 8;
-    const dim3 grid((unsigned)(8 * per)), block(256);
+    const dim3 grid((unsigned)xcd_grid(a.ntiles)), block(256);
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = ensure_lds(reinterpret_cast<const void *>(kern), lds);
         if (e != hipSuccess) return e;
@@ -801,7 +796,7 @@ hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work
     const int nt = (threads == 64 || threads == 128) ? threads : 256;
     const int64_t items = 8 * ((total + 7) / 8);
     const bool persist = grid_wgs > 0 && grid_wgs < items;
-    const dim3 grid((unsigned)(persist ? std::max(8, grid_wgs & ~7) : items)), block(nt);
+    const dim3 grid((unsigned)(persist ? std::max(8, grid_wgs & ~7) : xcd_grid(total))), block(nt);
     const bool mixed = k == TileKern::Mixed;
 #define NSA_LAUNCH_BATCH(T, N, P) \
     hipLaunchKernelGGL((k_tiled_batch<T, N, P>), grid, block, (size_t)lds, s, desc, work, total)
