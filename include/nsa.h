@@ -237,9 +237,11 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
 typedef struct nsa_batch nsa_batch; /* opaque */
 
 /* Many uploaded meshes (uneven sizes) assembled by one launch of the tiled kernel over the
- * concatenated tile lists of all meshes (each mesh's tiles contiguous, every XCD a contiguous slice;
- * one workgroup per tile or a persistent grid, see nsa_assemble_batched). Every mesh must be uploaded on the current device and
- * have a tile plan for `scatter` (NSA_EUNSUPPORTED otherwise). The meshes must outlive the batch. */
+ * concatenated tile lists of all meshes (each mesh's tiles contiguous; one workgroup per tile, every
+ * XCD taking runs of 16 consecutive items from the whole list, or a persistent grid, every XCD
+ * walking a contiguous eighth; see nsa_assemble_batched). Every mesh must be uploaded on the current
+ * device and have a tile plan for `scatter` (NSA_EUNSUPPORTED otherwise). The meshes must outlive
+ * the batch. */
 nsa_status nsa_batch_create(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, nsa_batch **out);
 nsa_status nsa_batch_destroy(nsa_batch *b);
 /* A reusable batch for continuous batching: room for up to max_meshes members with max_tiles tiles of
