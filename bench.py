@@ -221,7 +221,7 @@ def run_batch(args):
     nelem = sum(m.nelem for m in ms_)
     log(f"batch of {len(ms_)} meshes, {nelem} tets ({time.perf_counter() - t0:.1f} s)")
     tuned = autotune.tune_batch(ms_, scat, prec, cache=None, log=log,
-                                tile_candidates=(384, 512) if scat == nsa.ATOMIC else (160, 256))
+                                tile_candidates=(336, 384, 512) if scat == nsa.ATOMIC else (160, 256))
     log(f"autotuned: {({k: tuned[k] for k in ('tile_blocks', 'block_threads', 'grid_wgs', 'ms')})}")
     handles, b, vels, outs = autotune.build_batch(ms_, tuned["tile_blocks"], scat)
     nt = tuned["block_threads"] if scat == nsa.ATOMIC else 0

@@ -60,7 +60,7 @@ def build_batch(meshes, tile_blocks, scatter, device="cuda"):
     return handles, b, vels, outs
 
 
-def tune_batch(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, tile_candidates=(384, 512),
+def tune_batch(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, tile_candidates=(336, 384, 512),
                thread_candidates=(128, 256), grid_per_cu=(0, 1, 2), reps=5, cache: str | None = DEFAULT_CACHE,
                log=None) -> dict:
     """Best (tile_blocks, block_threads, grid_wgs) for this batch; cached by signature(). A grid
