@@ -275,19 +275,20 @@ def run_serve(args):
     device from the request's seed and its own rho, mu, dt. The arrival rate is set to a fraction of
     the batched form's throughput on the 64-mesh batch (measured first, same run). The server runs
     continuous batching (mixed precision); beside it, plain FP64 launches served one at a time on
-    the same resident meshes and the same arrival stream."""
+    the same meshes (resident with the FP64 kernel's own plan) and the same arrival stream."""
     import math
     import threading
     import torch
     from paper_2111_05651_amd import inputs, nsa
-    from paper_2111_05651_amd.serve import DONE, GpuExecutor, Server
+    from paper_2111_05651_amd.serve import DONE, GpuExecutor, Server, default_tile_blocks
     scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
     prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
-    # reference rate: the 64-mesh batch, one launch (default plan)
+    # reference rate: the 64-mesh batch, one launch, with the plan the served meshes use
     t0 = time.perf_counter()
     c4 = inputs.config_batch()
-    hs = [nsa.Mesh.from_inputs(m, tile_blocks=None if scat == nsa.ATOMIC else 0,
-                               tile_blocks_colour=0 if scat == nsa.ATOMIC else None).upload() for m in c4]
+    tb = default_tile_blocks(scat, prec)
+    hs = [nsa.Mesh.from_inputs(m, tile_blocks=tb if scat == nsa.ATOMIC else 0,
+                               tile_blocks_colour=0 if scat == nsa.ATOMIC else tb).upload() for m in c4]
     b = nsa.Batch(hs, scat)
     vels = [torch.from_numpy(m.velocity).cuda() for m in c4]
     outs = b.alloc_outputs()
@@ -304,9 +305,15 @@ def run_serve(args):
         f"({time.perf_counter() - t0:.1f} s)")
     ex = GpuExecutor(meshes, scatter=scat, precision=prec, slots=args.serve_slots, trace=True, log=log)
     sizes = [(h.nelem, h.npoin, h.nnzb) for h in ex.meshes]
-    del meshes
     log(f"resident: {ex.resident_bytes / 1e9:.2f} GB ({time.perf_counter() - t0:.1f} s)")
-    plain = GpuExecutor(None, scatter=scat, precision=nsa.FP64, mode="plain", trace=True, resident=ex.meshes)
+    # the plain FP64 comparison keeps meshes of its own when the served plan is not the FP64 kernel's
+    if default_tile_blocks(scat, prec) == default_tile_blocks(scat, nsa.FP64, "plain"):
+        plain = GpuExecutor(None, scatter=scat, precision=nsa.FP64, mode="plain", trace=True, resident=ex.meshes)
+    else:
+        plain = GpuExecutor(meshes, scatter=scat, precision=nsa.FP64, mode="plain", trace=True, log=log)
+        log(f"plain comparison: own resident meshes, {plain.resident_bytes / 1e9:.2f} GB "
+            f"({time.perf_counter() - t0:.1f} s)")
+    del meshes
     mean_elems = sum(x[0] for x in sizes) / len(sizes)
 
     def run(executor, frac, seed):

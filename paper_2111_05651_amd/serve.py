@@ -46,6 +46,15 @@ QUEUED, ADMITTED, RUNNING, DONE, REJECTED, TIMEOUT, FAILED = (
 ALIGN = 256
 
 
+def default_tile_blocks(scatter: int, precision: int, mode: str = "batched") -> int | None:
+    """Tile size of the resident meshes' plan: 336 blocks for batched mixed-precision atomic work (52.5
+    KB of LDS, so three 256-thread workgroups share a CU, which the mixed kernel's register count
+    allows), otherwise None (the library's default plan)."""
+    if mode == "batched" and scatter == nsa.ATOMIC and precision == nsa.MIXED:
+        return 336
+    return None
+
+
 def align(n: int) -> int:
     return (int(n) + ALIGN - 1) // ALIGN * ALIGN
 
@@ -479,8 +488,8 @@ class GpuExecutor:
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.slots = int(slots)
-        # the library's default plan size unless given (None leaves it to the library)
-        tb = tile_blocks
+        # the plan size for this mode and precision unless given (None leaves it to the library)
+        tb = tile_blocks if tile_blocks is not None else default_tile_blocks(self.scatter, self.precision, mode)
         self.meshes = list(resident) if resident is not None else []
         self.shared = resident is not None
         t0 = time.perf_counter()
