@@ -493,8 +493,9 @@ def main():
         log(f"mesh registered: nnzb={info.nnzb} gather tiles={info.gather_ntiles} records/nelem="
             f"{info.gather_records / max(m.nelem, 1):.2f} lds={list(info.gather_lds_bytes)}")
     else:
-        log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} tile_elems/nelem="
-            f"{info.tile_elems[scat] / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes[scat]}")
+        log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} runs={info.tile_runs[scat]} "
+            f"(pairs per run {4 * m.nelem / max(info.tile_runs[scat], 1):.2f}) max runs per tile "
+            f"{info.tile_max_runs[scat]} lds={info.tile_lds_bytes[scat]}")
     vel = torch.from_numpy(m.velocity).to("cuda:0")
     values, rhs = mesh.alloc_outputs("cuda:0")
     stream = torch.cuda.current_stream()

@@ -99,10 +99,11 @@ typedef struct nsa_mesh_info {
     int64_t max_row_blocks;    /* largest row degree of the block pattern */
     /* row-tile plans of the tiled kernel, indexed by scatter mode (NSA_ATOMIC, NSA_COLOUR) */
     int64_t ntiles[2];         /* number of tiles (0 if the mesh cannot use the tiled kernel) */
-    int64_t tile_elems[2];     /* sum over tiles of the elements each tile evaluates */
+    int64_t tile_runs[2];      /* runs over all tiles (see nsa_mesh_get_tiles) */
     int32_t tile_blocks[2];    /* requested tile size (LDS budget tile_blocks * 160 bytes) */
-    int32_t tile_threads[2];   /* workgroup size of the plan */
-    int32_t tile_max_colours[2]; /* largest number of tile-local colours */
+    int32_t tile_threads[2];   /* workgroup size of the plan (a tile holds at most this many runs,
+                                  unless one row alone has more) */
+    int32_t tile_max_runs[2];  /* largest number of runs in one tile */
     int32_t tile_lds_bytes[2]; /* LDS a workgroup uses (largest tile) */
     /* gather plan (NSA_KERNEL_GATHER) */
     int64_t gather_ntiles;     /* 0 if there is none */
@@ -127,8 +128,8 @@ const char *nsa_status_string(nsa_status st);
 /* Detail of the last failure on this thread ("" if none). Valid until the next libnsa call on the
  * same thread. */
 const char *nsa_last_error(void);
-/* Library version as major*10000 + minor*100 + patch (201 = 0.2.1: nsa_assemble_batched takes
- * grid_wgs 0 as one workgroup per tile). */
+/* Library version as major*10000 + minor*100 + patch (300 = 0.3.0: the tiled kernel walks runs of
+ * elements around an edge, nsa_mesh_get_tiles returns run records). */
 int32_t nsa_version(void);
 
 /* ---- block pattern of the node graph (host, standalone) ------------------------------------- */
@@ -157,14 +158,13 @@ nsa_status nsa_pattern_fill(int64_t npoin, int64_t nelem, const int32_t *lnods, 
 nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
                            nsa_mesh **out);
 /* Re-plan the row tiles the tiled kernel uses for one scatter mode. A tile is a contiguous range of
- * block rows whose LDS footprint (136 bytes per block, 44 per row, 48 per touched node) stays within
- * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB). A tile's elements are
- * every element with a node in it, coloured so that elements of one tile colour share no owned
- * node. Defaults: 512 (NSA_ATOMIC, 256-thread workgroups) and 160 (NSA_COLOUR, one wavefront per
- * tile); tile_blocks = 0 drops the plan of that mode (the tiled kernel then refuses the mode and
- * NSA_KERNEL_AUTO falls back to the direct kernel). Plans are built on first need
- * (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be called before nsa_mesh_upload
- * (NSA_ESTATE after). */
+ * block rows whose LDS footprint (136 bytes per block, 40 per row, 48 per touched node) stays within
+ * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB) and whose runs (see
+ * nsa_mesh_get_tiles) number at most the plan's workgroup size. Defaults: 512 (NSA_ATOMIC, 256-thread
+ * workgroups) and 160 (NSA_COLOUR, one wavefront per tile); tile_blocks = 0 drops the plan of that
+ * mode (the tiled kernel then refuses the mode and NSA_KERNEL_AUTO falls back to the direct kernel).
+ * Plans are built on first need (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be
+ * called before nsa_mesh_upload (NSA_ESTATE after). */
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks);
 /* With scatter = NSA_GATHER_PLAN the call sizes the gather plan instead, which is not built unless
  * asked for: contiguous row ranges of at most tile_blocks blocks (64..4096; 0 drops the plan), 4095
@@ -190,16 +190,21 @@ nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol,
 nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems);
 /* Row-tile plan of one scatter mode (host arrays sized from nsa_mesh_get_info with k = scatter; any
  * may be NULL): tile_row int32 [ntiles+1] (tile t owns rows tile_row[t] .. tile_row[t+1]-1),
- * tile_eptr int64 [ntiles+1] (record offsets), elems int32 [tile_elems] (element of each record),
- * colours int32 [tile_elems] (its tile-local colour), tile_nptr int64 [ntiles+1] and tile_nodes
- * int32 [tile_nptr[ntiles]] (the owned rows of tile t first, as local ids 0 .. nrows-1, then the
- * other nodes its elements touch, ascending), records 24 bytes per record: uint16 local node
- * ids[4] (owned nodes first), then uint8 ranks[4][4] where ranks[k][b] is the position of column
- * node b inside the row of the k-th owned node (zero for rows the tile does not own).
+ * tile_rptr int64 [ntiles+1] (run offsets), run_elems int32 [tile_runs][4] (the elements of each
+ * run in order, -1 past its length), tile_nptr int64 [ntiles+1] and tile_nodes int32
+ * [tile_nptr[ntiles]] (the owned rows of tile t first, as local ids 0 .. nrows-1, then the other
+ * nodes its elements touch, ascending), runs 32 bytes per run (uint16 fields, local node ids and
+ * block slots relative to the tile's first block bptr[tile_row[t]]):
+ *   row, hinge, k0, len, diag, jslot, last, 0, knew[4], kslot[4].
+ * Every pair (element e, row i) with e containing the node i of a tile's row lies in exactly one run
+ * of that tile; the run's element q has the vertices (row, hinge, k_old(q), knew[q]) with
+ * k_old(0) = k0 and k_old(q) = knew[q-1]; kslot[q] is the slot of block (row, k_old(q)), diag of
+ * (row, row), jslot of (row, hinge), last of (row, knew[len-1]). One lane of the kernel walks a run,
+ * integrates row `row` of each of its elements, sums the blocks (row, row), (row, hinge) and the RHS
+ * row over the run in registers and carries block (row, knew[q]) to the next element.
  * NSA_EUNSUPPORTED if the mesh has no plan for that mode. */
-nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
-                              int32_t *elems, int32_t *colours, int64_t *tile_nptr, int32_t *tile_nodes,
-                              uint8_t *records);
+nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_rptr,
+                              int32_t *run_elems, int64_t *tile_nptr, int32_t *tile_nodes, uint8_t *runs);
 /* Gather plan (sizes from nsa_mesh_get_info; any array may be NULL): tile_row int32 [ntiles+1],
  * tile_nptr int64 [ntiles+1] and tile_nodes int32 (node tables as for the row tiles), tile_eptr
  * int64 [ntiles+1], elems int32 [gather_records] (element of each record, ascending inside a tile),

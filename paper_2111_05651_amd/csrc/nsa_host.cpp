@@ -346,25 +346,254 @@ void bank_order(const nsa_mesh *m, const std::vector<int32_t> &els, const std::v
     }
 }
 
+// ---- run plan of the tiled kernel ------------------------------------------------------------
+
+// A run in global node ids (see nsa::RunRec): row i, hinge j, k_old of its first element, and per
+// element its id and k_new.
+struct GRun {
+    int32_t row, hinge, k0, len;
+    int32_t el[nsa::kRunMax], knew[nsa::kRunMax];
+};
+
+// Partition the elements around node i (star[0 .. ns)) into runs of at most kRunMax elements. The
+// elements that contain both i and a node j form the ring of the edge (i, j); two of them are
+// neighbours in the ring when they share a face (i, j, k). Greedy: among all hinges j, walk the
+// longest chain of still unassigned ring neighbours (cut at kRunMax), preferring a chain that is
+// complete within kRunMax (the ring of a face-diagonal edge of a Kuhn cube has four elements, and
+// those six rings partition the 24 elements around an interior node), then the shortest complete
+// chain; take it as one run and repeat. Any chain is correct; the choice only sets how many runs a
+// row needs (each run costs one set of register sums to add into the tile image).
+void row_runs(const nsa_mesh *m, int32_t i, const int32_t *star, int64_t ns, std::vector<GRun> &out) {
+    struct El {
+        int32_t e, v[3];  // element and its three vertices other than i
+        bool used;
+    };
+    std::vector<El> els((size_t)ns);
+    std::vector<int32_t> hinges;
+    for (int64_t q = 0; q < ns; q++) {
+        const int32_t *ln = &m->lnods[4 * (int64_t)star[q]];
+        El &x = els[(size_t)q];
+        x.e = star[q];
+        x.used = false;
+        int c = 0;
+        for (int a = 0; a < 4; a++)
+            if (ln[a] != i && c < 3) x.v[c++] = ln[a];
+        hinges.insert(hinges.end(), x.v, x.v + 3);
+    }
+    std::sort(hinges.begin(), hinges.end());
+    hinges.erase(std::unique(hinges.begin(), hinges.end()), hinges.end());
+    // the two vertices of element x other than i and j (j is one of x.v)
+    auto others = [](const El &x, int32_t j, int32_t &a, int32_t &b) {
+        int c = 0;
+        int32_t o[2] = {-1, -1};
+        for (int q = 0; q < 3; q++)
+            if (x.v[q] != j && c < 2) o[c++] = x.v[q];
+        a = o[0];
+        b = o[1];
+    };
+    auto has = [](const El &x, int32_t g) { return x.v[0] == g || x.v[1] == g || x.v[2] == g; };
+    std::vector<int32_t> ring, chain, kn, best_chain, best_kn;
+    std::vector<char> seen;
+    int64_t left = ns;
+    while (left > 0) {
+        int32_t best_j = -1, best_k0 = -1;
+        int best_take = 0, best_full = 0;
+        bool best_fits = false;
+        for (int32_t j : hinges) {
+            ring.clear();
+            for (size_t q = 0; q < els.size(); q++)
+                if (!els[q].used && has(els[q], j)) ring.push_back((int32_t)q);
+            if (ring.empty()) continue;
+            const size_t rn = ring.size();
+            // ring neighbours share a vertex besides i and j; walk every chain once, from an end
+            // (an element with at most one neighbour) or, for a closed ring, from any element
+            std::vector<int32_t> ka(rn), kb(rn), deg(rn, 0);
+            for (size_t q = 0; q < rn; q++) others(els[(size_t)ring[q]], j, ka[q], kb[q]);
+            for (size_t q = 0; q < rn; q++)
+                for (size_t p = 0; p < rn; p++)
+                    if (p != q && (ka[p] == ka[q] || ka[p] == kb[q] || kb[p] == ka[q] || kb[p] == kb[q])) deg[q]++;
+            seen.assign(rn, 0);
+            for (int pass = 0; pass < 2; pass++) {
+                for (size_t s0 = 0; s0 < rn; s0++) {
+                    if (seen[s0] || (pass == 0 && deg[s0] > 1)) continue;
+                    // leave the start through a vertex it shares with a neighbour, if any
+                    int32_t k0 = ka[s0], k1 = kb[s0];
+                    bool out_b = false;
+                    for (size_t p = 0; p < rn && !out_b; p++)
+                        if (p != s0 && (ka[p] == kb[s0] || kb[p] == kb[s0])) out_b = true;
+                    if (!out_b) std::swap(k0, k1);
+                    chain.assign(1, (int32_t)s0);
+                    kn.assign(1, k1);
+                    seen[s0] = 1;
+                    int32_t kcur = k1;
+                    while (true) {
+                        size_t nx = rn;
+                        for (size_t p = 0; p < rn; p++)
+                            if (!seen[p] && (ka[p] == kcur || kb[p] == kcur)) {
+                                nx = p;
+                                break;
+                            }
+                        if (nx == rn) break;
+                        const int32_t knext = ka[nx] == kcur ? kb[nx] : ka[nx];
+                        seen[nx] = 1;
+                        chain.push_back((int32_t)nx);
+                        kn.push_back(knext);
+                        kcur = knext;
+                    }
+                    const int full = (int)chain.size();
+                    const int take = std::min(full, nsa::kRunMax);
+                    const bool fits = full <= nsa::kRunMax;
+                    const bool better = take > best_take || (take == best_take && fits && !best_fits) ||
+                                        (take == best_take && fits == best_fits && full < best_full);
+                    if (better) {
+                        best_take = take;
+                        best_full = full;
+                        best_fits = fits;
+                        best_j = j;
+                        best_k0 = k0;
+                        best_chain.clear();
+                        for (int q = 0; q < take; q++) best_chain.push_back(ring[(size_t)chain[(size_t)q]]);
+                        best_kn.assign(kn.begin(), kn.begin() + take);
+                    }
+                }
+            }
+        }
+        GRun r{};
+        r.row = i;
+        r.hinge = best_j;
+        r.k0 = best_k0;
+        r.len = best_take;
+        for (int q = 0; q < nsa::kRunMax; q++) {
+            r.el[q] = q < best_take ? els[(size_t)best_chain[(size_t)q]].e : -1;
+            r.knew[q] = q < best_take ? best_kn[(size_t)q] : -1;
+        }
+        for (int q = 0; q < best_take; q++) els[(size_t)best_chain[(size_t)q]].used = true;
+        left -= best_take;
+        out.push_back(r);
+    }
+}
+
+// Order of the runs of a tile (their lanes): length descending, so that the lanes of a wavefront
+// walk runs of the same length; inside each wavefront's 64 runs, groups of 16 consecutive runs (the lanes whose
+// 8-byte LDS atomics the LDS serves together: 16 lanes over 32 four-byte banks) chosen greedily so
+// that the runs of a group belong to different rows (same row: the same diagonal block, RHS row and
+// possibly the same (i, k) blocks, i.e. the same addresses, which the LDS serialises) and that, for
+// every add instruction, their target slots fall on different bank pairs (value v of slot s lies on
+// bank pair (s + v) mod 16 with the 17-double slot stride; RHS row r on (5 r + c) mod 16).
+void run_order(const std::vector<nsa::RunRec> &runs, std::vector<int32_t> &order) {
+    constexpr int kGroup = 16, kWave = 64, kTypes = nsa::kRunMax + 4;
+    const size_t n = runs.size();
+    // start from the rows interleaved (the first run of every row, then the second, ...), so that a
+    // window of consecutive candidates spans many rows
+    std::vector<int32_t> base(n), ordinal(n);
+    {
+        std::unordered_map<int, int> seen;
+        for (size_t q = 0; q < n; q++) ordinal[q] = seen[runs[q].row]++;
+    }
+    for (size_t q = 0; q < n; q++) base[q] = (int32_t)q;
+    std::stable_sort(base.begin(), base.end(), [&](int32_t x, int32_t y) {
+        if (runs[x].len != runs[y].len) return runs[x].len > runs[y].len;
+        if (ordinal[x] != ordinal[y]) return ordinal[x] < ordinal[y];
+        return runs[x].row < runs[y].row;
+    });
+    order.clear();
+    order.reserve(n);
+    uint8_t cnt[kTypes][kGroup];
+    std::vector<int32_t> rows;
+    int fill = kGroup;
+    auto slot_of = [&](const nsa::RunRec &r, int t) -> int {
+        if (t < nsa::kRunMax) return t < r.len ? r.kslot[t] : -1;
+        switch (t - nsa::kRunMax) {
+            case 0: return r.last;
+            case 1: return r.jslot;
+            case 2: return r.diag;
+            default: return 5 * r.row;
+        }
+    };
+    auto cost = [&](const nsa::RunRec &r) -> int {
+        int c = 256 * (int)std::count(rows.begin(), rows.end(), (int32_t)r.row);
+        for (int t = 0; t < kTypes; t++) {
+            const int s = slot_of(r, t);
+            if (s >= 0) c += cnt[t][s & (kGroup - 1)];
+        }
+        return c;
+    };
+    size_t head = 0;
+    while (head < n) {
+        if (fill == kGroup) {
+            std::memset(cnt, 0, sizeof cnt);
+            rows.clear();
+            fill = 0;
+        }
+        size_t best = head;
+        int bestc = 1 << 30;
+        const size_t wave_end = std::min(n, (head / kWave + 1) * kWave);
+        for (size_t q = head; q < wave_end; q++) {
+            const int c = cost(runs[base[q]]);
+            if (c < bestc) {
+                bestc = c;
+                best = q;
+            }
+            if (!c) break;
+        }
+        const nsa::RunRec &r = runs[base[best]];
+        for (int t = 0; t < kTypes; t++) {
+            const int s = slot_of(r, t);
+            if (s >= 0) cnt[t][s & (kGroup - 1)]++;
+        }
+        rows.push_back(r.row);
+        order.push_back(base[best]);
+        std::swap(base[best], base[head]);  // inside one wavefront's 64 runs
+        head++;
+        fill++;
+    }
+}
+
 // Row tiles for the tiled kernel (see nsa_internal.h). A tile is a contiguous row range whose LDS
-// footprint (block image, RHS rows, row offsets, node table) stays within tile_blocks * 160 bytes.
+// footprint (block image, RHS rows, node table) stays within tile_blocks * 160 bytes and whose runs
+// number at most `threads` (one run per lane; a single row with more runs takes several rounds).
 // Per tile: the nodes its elements touch (the owned rows first, as local ids 0 .. nrows-1, then the
-// other nodes ascending), a greedy colouring of its elements (elements of one tile colour share no
-// owned node), and one 24-byte record per element with its local node ids (owned nodes first) and
-// the in-row ranks of its owned rows. Record order (both plans): owned-row count descending (the
-// lanes of a wavefront run the same number of row iterations), then the bank-aware order of
-// bank_order() inside each count. The deterministic plan needs no particular order: one wavefront
-// integrates the tile, so its LDS adds happen in the plan's fixed order whatever that order is.
+// other nodes ascending) and the runs of its rows in the order of run_order().
 nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads) {
     P = nsa::TilePlan();
     P.tile_blocks = tile_blocks;
     P.threads = threads;
-    // uint8 in-row ranks and uint16 local node ids bound what the tiled kernel can address
+    // uint16 slots and local node ids bound what the tiled kernel can address
     if (m->max_row_blocks > 256 || m->npoin == 0) return NSA_OK;
     const int64_t np = m->npoin;
     const int64_t one_row = (int64_t)nsa::tile_lds_bytes((int32_t)m->max_row_blocks, 1, (int32_t)m->max_row_blocks);
     if (one_row > kMaxTileLds) return NSA_OK;  // a single row would not fit in LDS
     const int64_t budget = std::max<int64_t>(std::min<int64_t>((int64_t)tile_blocks * 160, kMaxTileLds), one_row);
+    std::vector<int64_t> n2e_ptr;
+    std::vector<int32_t> n2e;
+    node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
+    // runs of every row (independent of the tiling)
+    std::vector<std::vector<GRun>> rr((size_t)host_threads());
+    std::vector<int64_t> row_nruns((size_t)np + 1, 0);
+    {
+        const int nth = host_threads();
+        const int64_t chunk = (np + nth - 1) / nth;
+        std::vector<std::thread> th;
+        for (int c = 0; c < nth; c++) {
+            const int64_t b = c * chunk, e = std::min<int64_t>(np, b + chunk);
+            if (b >= e) continue;
+            th.emplace_back([&, c, b, e] {
+                for (int64_t i = b; i < e; i++) {
+                    const size_t before = rr[(size_t)c].size();
+                    row_runs(m, (int32_t)i, n2e.data() + n2e_ptr[i], n2e_ptr[i + 1] - n2e_ptr[i], rr[(size_t)c]);
+                    row_nruns[(size_t)i + 1] = (int64_t)(rr[(size_t)c].size() - before);
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    for (int64_t i = 0; i < np; i++) row_nruns[(size_t)i + 1] += row_nruns[(size_t)i];
+    std::vector<GRun> allruns;
+    allruns.reserve((size_t)row_nruns[(size_t)np]);
+    for (auto &v : rr) {
+        allruns.insert(allruns.end(), v.begin(), v.end());
+        std::vector<GRun>().swap(v);
+    }
     // grow tiles row by row; the touched nodes of a tile are the columns of its rows
     std::vector<int32_t> stamp(np, -1);
     P.row.push_back(0);
@@ -376,7 +605,8 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
             for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) add += stamp[m->bcol[k]] != tid;
             const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
             const int64_t need = (int64_t)nsa::tile_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
-            if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows)) break;
+            const int64_t nruns = row_nruns[(size_t)r1 + 1] - row_nruns[(size_t)r0];
+            if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows || nruns > threads)) break;
             for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
             nodes += add;
             r1++;
@@ -386,135 +616,91 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
         P.cap_rows = std::max<int32_t>(P.cap_rows, (int32_t)(r1 - r0));
         P.cap_blocks = std::max<int32_t>(P.cap_blocks, (int32_t)(m->bptr[r1] - m->bptr[r0]));
         P.cap_nodes = std::max<int32_t>(P.cap_nodes, (int32_t)nodes);
+        P.cap_runs = std::max<int32_t>(P.cap_runs, (int32_t)(row_nruns[(size_t)r1] - row_nruns[(size_t)r0]));
         P.lds = std::max<int64_t>(P.lds, (int64_t)nsa::tile_lds_bytes((int32_t)(m->bptr[r1] - m->bptr[r0]),
                                                                       (int32_t)(r1 - r0), (int32_t)nodes));
         r0 = r1;
     }
     std::vector<int32_t>().swap(stamp);
     const int64_t nt = (int64_t)P.row.size() - 1;
-    std::vector<int64_t> n2e_ptr;
-    std::vector<int32_t> n2e;
-    node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
     struct Out {
-        std::vector<int32_t> els, col, nodes;
-        std::vector<nsa::TileRec> recs;
-        std::vector<int64_t> cnt, ncnt;  // per tile record / node counts
-        int32_t maxcol = 0;
+        std::vector<int32_t> nodes, relems;
+        std::vector<nsa::RunRec> runs;
+        std::vector<int64_t> cnt, ncnt;
+        int64_t pairs = 0;
     };
     std::vector<Out> outs(host_threads());
     int used = parallel_chunks(nt, [&](int ci, int64_t tb, int64_t te) {
         Out &o = outs[ci];
-        std::vector<int32_t> els, col, nown, idx, other, sched;
-        std::vector<int8_t> vord;
-        std::vector<uint64_t> mask;
+        std::vector<int32_t> other, order;
+        std::vector<nsa::RunRec> loc;
+        std::vector<int32_t> locel;
         for (int64_t t = tb; t < te; t++) {
             const int32_t r0 = P.row[t], r1 = P.row[t + 1], nr = r1 - r0;
-            els.clear();
-            for (int32_t i = r0; i < r1; i++) els.insert(els.end(), n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
-            std::sort(els.begin(), els.end());
-            els.erase(std::unique(els.begin(), els.end()), els.end());
-            const size_t ne = els.size();
-            // node table: owned rows, then the other touched nodes ascending
+            const int64_t b0 = m->bptr[r0];
+            // node table: owned rows, then the other touched nodes (columns of the rows) ascending
             other.clear();
-            for (int32_t e : els)
-                for (int a = 0; a < 4; a++) {
-                    const int32_t g = m->lnods[4 * (int64_t)e + a];
-                    if (g < r0 || g >= r1) other.push_back(g);
-                }
+            for (int32_t i = r0; i < r1; i++)
+                for (int64_t k = m->bptr[i]; k < m->bptr[i + 1]; k++)
+                    if (m->bcol[k] < r0 || m->bcol[k] >= r1) other.push_back(m->bcol[k]);
             std::sort(other.begin(), other.end());
             other.erase(std::unique(other.begin(), other.end()), other.end());
             for (int32_t i = r0; i < r1; i++) o.nodes.push_back(i);
             o.nodes.insert(o.nodes.end(), other.begin(), other.end());
             o.ncnt.push_back((int64_t)nr + (int64_t)other.size());
-            auto local = [&](int32_t g) -> int32_t {
-                if (g >= r0 && g < r1) return g - r0;
-                return nr + (int32_t)(std::lower_bound(other.begin(), other.end(), g) - other.begin());
+            auto local = [&](int32_t g) -> uint16_t {
+                if (g >= r0 && g < r1) return (uint16_t)(g - r0);
+                return (uint16_t)(nr + (std::lower_bound(other.begin(), other.end(), g) - other.begin()));
             };
-            // greedy colouring in element order: conflicts are shared owned nodes
-            col.assign(ne, 0);
-            nown.assign(ne, 0);
-            mask.assign(2 * (size_t)nr, 0);
-            for (size_t j = 0; j < ne; j++) {
-                const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
-                uint64_t f0 = 0, f1 = 0;
-                for (int a = 0; a < 4; a++) {
-                    int32_t l = ln[a] - r0;
-                    if (l < 0 || l >= nr) continue;
-                    nown[j]++;
-                    f0 |= mask[2 * l];
-                    f1 |= mask[2 * l + 1];
+            auto slot = [&](int32_t i, int32_t g) -> uint16_t {
+                const int32_t *lo = m->bcol.data() + m->bptr[i], *hi = m->bcol.data() + m->bptr[i + 1];
+                return (uint16_t)(m->bptr[i] - b0 + (std::lower_bound(lo, hi, g) - lo));
+            };
+            loc.clear();
+            locel.clear();
+            for (int64_t q = row_nruns[(size_t)r0]; q < row_nruns[(size_t)r1]; q++) {
+                const GRun &g = allruns[(size_t)q];
+                nsa::RunRec r{};
+                r.row = (uint16_t)(g.row - r0);
+                r.hinge = local(g.hinge);
+                r.k0 = local(g.k0);
+                r.len = (uint16_t)g.len;
+                r.diag = slot(g.row, g.row);
+                r.jslot = slot(g.row, g.hinge);
+                r.last = slot(g.row, g.knew[g.len - 1]);
+                for (int e = 0; e < nsa::kRunMax; e++) {
+                    r.knew[e] = e < g.len ? local(g.knew[e]) : 0;
+                    r.kslot[e] = e < g.len ? slot(g.row, e == 0 ? g.k0 : g.knew[e - 1]) : 0;
+                    locel.push_back(g.el[e]);
                 }
-                // more than 127 colours (an owned node in more than 127 of the tile's elements):
-                // the rest share colour 127. Tile colours are reported with the plan and only seed
-                // the record order (the atomics keep the sums right, the one-wavefront plan keeps
-                // them reproducible), so this costs nothing else.
-                int c;
-                if (~f0)
-                    c = __builtin_ctzll(~f0);
-                else if (~f1 && __builtin_ctzll(~f1) < 63)
-                    c = 64 + __builtin_ctzll(~f1);
-                else
-                    c = 127;
-                for (int a = 0; a < 4; a++) {
-                    int32_t l = ln[a] - r0;
-                    if (l >= 0 && l < nr) mask[2 * l + (c >> 6)] |= 1ull << (c & 63);
-                }
-                col[j] = c;
-                o.maxcol = std::max(o.maxcol, c + 1);
+                o.pairs += g.len;
+                loc.push_back(r);
             }
-            idx.resize(ne);
-            for (size_t j = 0; j < ne; j++) idx[j] = (int32_t)j;
-            std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-                if (nown[x] != nown[y]) return nown[x] > nown[y];
-                if (col[x] != col[y]) return col[x] < col[y];
-                return els[x] < els[y];
-            });
-            // vertex order of each record: owned first (ascending), then the others
-            vord.resize(4 * ne);
-            for (size_t j = 0; j < ne; j++) {
-                const int32_t *ln = &m->lnods[4 * (int64_t)els[j]];
-                int k = 0;
-                for (int a = 0; a < 4; a++)
-                    if (ln[a] >= r0 && ln[a] < r1) vord[4 * j + k++] = (int8_t)a;
-                for (int a = 0; a < 4; a++)
-                    if (!(ln[a] >= r0 && ln[a] < r1)) vord[4 * j + k++] = (int8_t)a;
+            run_order(loc, order);
+            for (int32_t q : order) {
+                o.runs.push_back(loc[(size_t)q]);
+                o.relems.insert(o.relems.end(), locel.begin() + nsa::kRunMax * q, locel.begin() + nsa::kRunMax * (q + 1));
             }
-            bank_order(m, els, nown, r0, false, idx, vord, sched);
-            idx.swap(sched);
-            for (int32_t j : idx) {
-                const int64_t e = els[j];
-                const int32_t *ln = &m->lnods[4 * e];
-                int ord[4];
-                for (int q = 0; q < 4; q++) ord[q] = vord[4 * j + q];
-                nsa::TileRec r{};
-                for (int q = 0; q < 4; q++) r.loc[q] = (uint16_t)local(ln[ord[q]]);
-                for (int q = 0; q < nown[j]; q++) {
-                    const int64_t rs = m->bptr[ln[ord[q]]];
-                    for (int b = 0; b < 4; b++) r.rank[q][b] = (uint8_t)(m->emap[16 * e + 4 * ord[q] + ord[b]] - rs);
-                }
-                o.els.push_back((int32_t)e);
-                o.col.push_back(col[j]);
-                o.recs.push_back(r);
-            }
-            o.cnt.push_back((int64_t)ne);
+            o.cnt.push_back((int64_t)loc.size());
         }
     });
-    P.eptr.assign(1, 0);
+    std::vector<GRun>().swap(allruns);
+    P.rptr.assign(1, 0);
     P.nptr.assign(1, 0);
     for (int i = 0; i < used; i++) {
         Out &o = outs[i];
         for (size_t k = 0; k < o.cnt.size(); k++) {
-            P.eptr.push_back(P.eptr.back() + o.cnt[k]);
+            P.rptr.push_back(P.rptr.back() + o.cnt[k]);
             P.nptr.push_back(P.nptr.back() + o.ncnt[k]);
         }
-        P.elems.insert(P.elems.end(), o.els.begin(), o.els.end());
-        P.colour.insert(P.colour.end(), o.col.begin(), o.col.end());
         P.nodes.insert(P.nodes.end(), o.nodes.begin(), o.nodes.end());
-        P.recs.insert(P.recs.end(), o.recs.begin(), o.recs.end());
-        P.max_colours = std::max(P.max_colours, o.maxcol);
+        P.runs.insert(P.runs.end(), o.runs.begin(), o.runs.end());
+        P.relems.insert(P.relems.end(), o.relems.begin(), o.relems.end());
+        P.npairs += o.pairs;
         o = Out();
     }
-    if ((int64_t)P.eptr.size() != nt + 1) return fail(NSA_EUNSUPPORTED, "tile plan inconsistent");
+    if ((int64_t)P.rptr.size() != nt + 1 || P.npairs != 4 * m->nelem)
+        return fail(NSA_EUNSUPPORTED, "tile plan inconsistent");
     P.ok = true;
     return NSA_OK;
 }
@@ -823,10 +1009,10 @@ void plan_layout(nsa_mesh *m) {
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
     for (nsa::TilePlan &P : m->plan) {
         take(P.r_row, P.ok ? P.row.size() * sizeof(int32_t) : 0);
-        take(P.r_eptr, P.ok ? P.eptr.size() * sizeof(int64_t) : 0);
+        take(P.r_rptr, P.ok ? P.rptr.size() * sizeof(int64_t) : 0);
         take(P.r_nptr, P.ok ? P.nptr.size() * sizeof(int64_t) : 0);
         take(P.r_nodes, P.ok ? P.nodes.size() * sizeof(int32_t) : 0);
-        take(P.r_recs, P.ok ? P.recs.size() * sizeof(nsa::TileRec) : 0);
+        take(P.r_runs, P.ok ? P.runs.size() * sizeof(nsa::RunRec) : 0);
         take(P.r_b0, P.ok ? P.row.size() * sizeof(int64_t) : 0);
         take(P.r_npad, P.ok ? (size_t)P.ntiles() * P.cap_nodes * sizeof(int32_t) : 0);
     }
@@ -908,7 +1094,7 @@ const char *nsa_status_string(nsa_status st) {
 
 const char *nsa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t nsa_version(void) { return 201; }
+int32_t nsa_version(void) { return 300; }
 
 nsa_status nsa_pattern_count(int64_t npoin, int64_t nelem, const int32_t *lnods, int64_t *bptr,
                              int64_t *nnzb) {
@@ -1081,10 +1267,10 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
     for (int k = 0; k < 2; k++) {
         const nsa::TilePlan &P = m->plan[k];
         info->ntiles[k] = P.ntiles();
-        info->tile_elems[k] = P.nrec();
+        info->tile_runs[k] = P.nruns();
         info->tile_blocks[k] = P.tile_blocks;
         info->tile_threads[k] = P.threads;
-        info->tile_max_colours[k] = P.max_colours;
+        info->tile_max_runs[k] = P.cap_runs;
         info->tile_lds_bytes[k] = P.ok ? (int32_t)P.lds : 0;
     }
     const nsa::GatherPlan &G = m->gplan;
@@ -1120,9 +1306,8 @@ nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_
     return ok();
 }
 
-nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
-                              int32_t *elems, int32_t *colours, int64_t *tile_nptr, int32_t *tile_nodes,
-                              uint8_t *records) {
+nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_rptr,
+                              int32_t *run_elems, int64_t *tile_nptr, int32_t *tile_nodes, uint8_t *runs) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_tiles: null mesh");
     if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
@@ -1131,12 +1316,11 @@ nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_
     const nsa::TilePlan &P = m->plan[scatter];
     if (!P.ok) return fail(NSA_EUNSUPPORTED, "no tile plan for this mesh");
     if (tile_row) std::copy(P.row.begin(), P.row.end(), tile_row);
-    if (tile_eptr) std::copy(P.eptr.begin(), P.eptr.end(), tile_eptr);
-    if (elems) std::copy(P.elems.begin(), P.elems.end(), elems);
-    if (colours) std::copy(P.colour.begin(), P.colour.end(), colours);
+    if (tile_rptr) std::copy(P.rptr.begin(), P.rptr.end(), tile_rptr);
+    if (run_elems) std::copy(P.relems.begin(), P.relems.end(), run_elems);
     if (tile_nptr) std::copy(P.nptr.begin(), P.nptr.end(), tile_nptr);
     if (tile_nodes) std::copy(P.nodes.begin(), P.nodes.end(), tile_nodes);
-    if (records) std::memcpy(records, P.recs.data(), P.recs.size() * sizeof(nsa::TileRec));
+    if (runs) std::memcpy(runs, P.runs.data(), P.runs.size() * sizeof(nsa::RunRec));
     return ok();
 }
 
@@ -1237,11 +1421,11 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         const Up ups[] = {{m->r_ln, ln.data()}, {m->r_coord, co.data()}, {m->r_emap, em.data()},
                           {m->r_ln_c, lnc.data()}, {m->r_emap_c, emc.data()},
                           {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
-                          {P0.r_row, P0.row.data()}, {P0.r_eptr, P0.eptr.data()}, {P0.r_nptr, P0.nptr.data()},
-                          {P0.r_nodes, P0.nodes.data()}, {P0.r_recs, P0.recs.data()},
+                          {P0.r_row, P0.row.data()}, {P0.r_rptr, P0.rptr.data()}, {P0.r_nptr, P0.nptr.data()},
+                          {P0.r_nodes, P0.nodes.data()}, {P0.r_runs, P0.runs.data()},
                           {P0.r_b0, b0v[0].data()}, {P0.r_npad, npad[0].data()},
-                          {P1.r_row, P1.row.data()}, {P1.r_eptr, P1.eptr.data()}, {P1.r_nptr, P1.nptr.data()},
-                          {P1.r_nodes, P1.nodes.data()}, {P1.r_recs, P1.recs.data()},
+                          {P1.r_row, P1.row.data()}, {P1.r_rptr, P1.rptr.data()}, {P1.r_nptr, P1.nptr.data()},
+                          {P1.r_nodes, P1.nodes.data()}, {P1.r_runs, P1.runs.data()},
                           {P1.r_b0, b0v[1].data()}, {P1.r_npad, npad[1].data()},
                           {G.r_row, G.row.data()}, {G.r_nptr, G.nptr.data()}, {G.r_nodes, G.nodes.data()},
                           {G.r_eptr, G.eptr.data()}, {G.r_recs, G.recs.data()}, {G.r_pptr, G.pptr.data()},
@@ -1290,10 +1474,9 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m) {
         std::vector<uint32_t>().swap(G.slots);
     }
     for (nsa::TilePlan &P : m->plan) {
-        std::vector<int32_t>().swap(P.elems);
-        std::vector<int32_t>().swap(P.colour);
+        std::vector<int32_t>().swap(P.relems);
         std::vector<int32_t>().swap(P.nodes);
-        std::vector<nsa::TileRec>().swap(P.recs);
+        std::vector<nsa::RunRec>().swap(P.runs);
     }
     m->host_released = true;
     return ok();
@@ -1373,8 +1556,8 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         t.ntiles = P.ntiles();
         t.lds_bytes = P.lds;
         t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
-        t.tile_eptr = (const int64_t *)(m->ws + P.r_eptr.off);
-        t.rec = (const uint2 *)(m->ws + P.r_recs.off);
+        t.tile_rptr = (const int64_t *)(m->ws + P.r_rptr.off);
+        t.runs = (const uint4 *)(m->ws + P.r_runs.off);
         t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
         t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
         t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
@@ -1674,8 +1857,8 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
             t.ntiles = P.ntiles();
             t.lds_bytes = P.lds;
             t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
-            t.tile_eptr = (const int64_t *)(m->ws + P.r_eptr.off);
-            t.rec = (const uint2 *)(m->ws + P.r_recs.off);
+            t.tile_rptr = (const int64_t *)(m->ws + P.r_rptr.off);
+            t.runs = (const uint4 *)(m->ws + P.r_runs.off);
             t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
             t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
             t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);

@@ -43,22 +43,31 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 
 // Row tiles: tile t owns the contiguous block rows [row[t], row[t+1]) and therefore the contiguous
 // blocks [bptr[r0], bptr[r1]). Its nodes tile_nodes[nptr[t] .. nptr[t+1]) are the owned rows (local
-// ids 0 .. nrows-1) followed by every other node its elements touch. Its elements (every element
-// with at least one node in the tile) are described by 24-byte records rec[eptr[t] .. eptr[t+1]):
-// local node ids with the owned nodes first, and for the k-th owned node the in-row ranks of the
-// four columns (in the same order).
-struct TileRec {
-    uint16_t loc[4];
-    uint8_t rank[4][4];
+// ids 0 .. nrows-1) followed by every other node its elements touch. Its work is a list of runs
+// runs[rptr[t] .. rptr[t+1]): every pair (element, owned row i) of the tile lies in exactly one
+// run. A run is a sequence of up to kRunMax elements that all contain the row node i and a second
+// node j (the hinge), each sharing a face (i, j, k) with the next one: element q of the run has the
+// vertices (i, j, k_old(q), k_new(q)) with k_old(0) = k0 and k_old(q+1) = k_new(q). One lane walks a
+// run and integrates only row i of each element, keeping in registers the sums of the diagonal block
+// (i, i), the RHS row i, the block (i, j) (every element of the run adds to it) and the block
+// (i, k_new(q)) (the next element adds to it again as its (i, k_old)); it adds into the tile's LDS
+// image once per element (the finished (i, k_old) block) and once per run for the rest.
+// Slots are block indices inside the tile (block bptr[r0] + slot); node fields are local node ids.
+constexpr int kRunMax = 4;
+struct RunRec {
+    uint16_t row, hinge, k0, len;      // local row i (= its local node id), hinge j, k_old(0), elements
+    uint16_t diag, jslot, last, pad;   // slots of (i, i), (i, j) and (i, k_new(len-1)); pad = 0
+    uint16_t knew[kRunMax];            // k_new(q)
+    uint16_t kslot[kRunMax];           // slot of (i, k_old(q))
 };
-static_assert(sizeof(TileRec) == 24, "tile record layout");
+static_assert(sizeof(RunRec) == 32, "run record layout");
 
 struct TileArgs {
     int64_t ntiles = 0;
     int64_t lds_bytes = 0;               // dynamic LDS per workgroup (the largest tile's layout)
     const int32_t *tile_row = nullptr;   // [ntiles+1]
-    const int64_t *tile_eptr = nullptr;  // [ntiles+1]
-    const uint2 *rec = nullptr;          // [sum] TileRec as 3 x uint2
+    const int64_t *tile_rptr = nullptr;  // [ntiles+1] run offsets
+    const uint4 *runs = nullptr;         // [sum] RunRec as 2 x uint4
     const int64_t *tile_nptr = nullptr;  // [ntiles+1]
     const int32_t *tile_nodes = nullptr; // [sum]
     // the prologue's loads without a dependent round trip: tile_b0[t] = bptr[tile_row[t]] ([ntiles+1])
@@ -77,15 +86,15 @@ struct TileArgs {
 };
 
 // LDS layout of a tile workgroup (sized per tile), in doubles from the start of dynamic LDS: the
-// block image at a padded stride of 17 doubles, the RHS rows at a stride of 5, the node table
-// (x, y, z, u, v, w) at a 16-byte aligned offset, then the int32 row offsets.
+// block image at a padded stride of 17 doubles, the RHS rows at a stride of 5, then the node table
+// (x, y, z, u, v, w) at a 16-byte aligned offset.
 constexpr int kBlkStride = 17;
 constexpr int kRhsStride = 5;
 __host__ __device__ constexpr int64_t lds_racc_off(int32_t nblk) { return (int64_t)kBlkStride * nblk; }
 __host__ __device__ constexpr int64_t lds_nodes_off(int32_t nblk, int32_t nrows) {
     return (lds_racc_off(nblk) + (int64_t)kRhsStride * nrows + 1) & ~int64_t(1);
 }
-__host__ __device__ constexpr int64_t lds_rowoff_off(int32_t nblk, int32_t nrows, int32_t nnodes) {
+__host__ __device__ constexpr int64_t lds_tile_doubles(int32_t nblk, int32_t nrows, int32_t nnodes) {
     return lds_nodes_off(nblk, nrows) + 6 * (int64_t)nnodes;
 }
 
@@ -221,20 +230,20 @@ struct ResPlan {
 // A row-tile plan for one scatter mode (host copy, then device regions after upload).
 struct TilePlan {
     int32_t tile_blocks = 0;     // requested tile size: LDS budget tile_blocks * 160 bytes
-    int32_t threads = 256;       // workgroup size the plan is meant for
+    int32_t threads = 256;       // workgroup size the plan is meant for (runs per tile at most this)
     bool ok = false;             // plan exists (the mesh fits the tiled kernel)
-    int32_t cap_blocks = 0, cap_rows = 0, cap_nodes = 0, max_colours = 0;
+    int32_t cap_blocks = 0, cap_rows = 0, cap_nodes = 0, cap_runs = 0;
     int64_t lds = 0;             // LDS bytes of the largest tile
+    int64_t npairs = 0;          // (element, row) pairs over all runs (4 nelem)
     std::vector<int32_t> row;    // [ntiles+1]
-    std::vector<int64_t> eptr;   // [ntiles+1]
-    std::vector<int32_t> elems;  // element ids in record order
-    std::vector<int32_t> colour; // tile-local colour of each record
+    std::vector<int64_t> rptr;   // [ntiles+1]
+    std::vector<RunRec> runs;    // [nruns]
+    std::vector<int32_t> relems; // [nruns][kRunMax] element of each run position (-1 past the run)
     std::vector<int64_t> nptr;   // [ntiles+1]
     std::vector<int32_t> nodes;
-    std::vector<TileRec> recs;
-    Region r_row, r_eptr, r_nptr, r_nodes, r_recs, r_b0, r_npad;
+    Region r_row, r_rptr, r_nptr, r_nodes, r_runs, r_b0, r_npad;
     int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
-    int64_t nrec() const { return ok ? eptr.back() : 0; }
+    int64_t nruns() const { return ok ? rptr.back() : 0; }
 };
 
 }  // namespace nsa

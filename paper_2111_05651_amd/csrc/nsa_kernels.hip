@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "nsa_device.h"
@@ -412,58 +413,197 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One element of the tile from its record: node data from the LDS node table, owned rows first.
-struct Rec {
-    uint2 w0, w1, w2;
-};
-
-__device__ __forceinline__ Rec load_rec(const TileArgs &A, int64_t p) {
-    return Rec{A.rec[3 * p], A.rec[3 * p + 1], A.rec[3 * p + 2]};
+// Coordinates and velocity of local node l from the tile's LDS node table.
+__device__ __forceinline__ void node_load(const double *nodes, int l, double X[3], double U[3]) {
+    const double2 *nd = reinterpret_cast<const double2 *>(nodes + 6 * l);
+    const double2 q0 = nd[0], q1 = nd[1], q2 = nd[2];
+    X[0] = q0.x;
+    X[1] = q0.y;
+    X[2] = q1.x;
+    U[0] = q1.y;
+    U[1] = q2.x;
+    U[2] = q2.y;
 }
 
+__device__ __forceinline__ void lds_add16(double *p, const double v[16]) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) lds_add(p + i, v[i]);
+}
+
+// Row 0 of an element (its local vertex 0 is the run's row node): what the four blocks (0, b) and the
+// RHS row need, reduced to per-column scalars so that the gradient products and the velocity die
+// before the blocks are formed. With d[k][b] = U_k . grad N_b and s_b = sum_k d[k][b] (see
+// element_row), for column b:
+//   T_b = (rho/dt) V/20 (1 + d_0b) + rho V/20 (s_b + d[0][b]) + mu V K_0b
+//         + tau1 rho (rho V/20 (s_0 s_b + gram_0b) + (rho/dt) V/20 (s_0 + d[b][0]))
+// and the block is uu = T_b I + mu V G_b G_0^T + tau2 V G_0 G_b^T, up = -V/4 G_0 + tau1 rho V/4 s_0 G_b,
+// pu = V/4 G_b + tau1 G_0 (rho V/4 s_b + (rho/dt) V/4), pp = tau1 V K_0b.
 template <typename R>
-__device__ __forceinline__ void tile_element(const TileArgs &A, const Rec &rc, int nrows, double *acc, double *racc,
-                                             const double *nodes, const int *rowoff) {
-    const uint2 w0 = rc.w0, w1 = rc.w1, w2 = rc.w2;
-    const int loc[4] = {(int)(w0.x & 0xffffu), (int)(w0.x >> 16), (int)(w0.y & 0xffffu), (int)(w0.y >> 16)};
-    const uint32_t rw[4] = {w1.x, w1.y, w2.x, w2.y};
-    int nown = 0;
+struct Row0 {
+    R gb[4][3];                         // grad N_b
+    R T[4], K[4], s[4];
+    R gm[3], gt[3], gmt[3], pa[3], tg[3];
+    R qa, v4, t1V, rv4, dv4;
+};
+
+template <typename R>
+__device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3], double rho_d, double mu_d,
+                                           double dt_d, Row0<R> &C, R rb[4]) {
+    R U[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; a++) nown += loc[a] < nrows;
-    double X[4][3], U[4][3];
+    for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        const double2 *nd = reinterpret_cast<const double2 *>(nodes + 6 * loc[a]);
-        const double2 q0 = nd[0], q1 = nd[1], q2 = nd[2];
-        X[a][0] = q0.x;
-        X[a][1] = q0.y;
-        X[a][2] = q1.x;
-        U[a][0] = q1.y;
-        U[a][1] = q2.x;
-        U[a][2] = q2.y;
+        for (int c = 0; c < 3; c++) {
+            U[a][c] = (R)Ud[a][c];
+            C.gb[a][c] = (R)g.G[a][c];
+        }
+    const R V = (R)g.V, h = (R)g.h, rh = (R)g.rh, rho = (R)rho_d, mu = (R)mu_d;
+    const R rdt = (R)(rho_d / dt_d);
+    R su[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) su[c] = U[0][c] + U[1][c] + U[2][c] + U[3][c];
+    const R an = (R)0.25 * sqrt(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
+    const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
+    const R t2 = mu + (R)0.5 * rho * an * h;
+    const R v4 = V * (R)0.25, v20 = V * (R)0.05, muV = mu * V, t2V = t2 * V, t1rho = t1 * rho;
+    const R Mo = rdt * v20, c1 = rho * v20, c2 = t1rho * rho * v20, c3 = t1rho * rdt * v20;
+    const R *g0 = C.gb[0];
+    R dk0[4];  // d[k][0]
+#pragma unroll
+    for (int k = 0; k < 4; k++) dk0[k] = U[k][0] * g0[0] + U[k][1] * g0[1] + U[k][2] * g0[2];
+    const R s0 = dk0[0] + dk0[1] + dk0[2] + dk0[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const R un = su[c] + U[0][c];
+        const R au = s0 * su[c] + dk0[0] * U[0][c] + dk0[1] * U[1][c] + dk0[2] * U[2][c] + dk0[3] * U[3][c];
+        rb[c] = rdt * v20 * (un + t1rho * au);
     }
-    Geo2 g;
-    geometry2(X, g);
-    ElemT<R> E;
-    setup_t<R>(g, U, A.rho, A.mu, A.dt, E);
+    rb[3] = t1 * rdt * v4 * s0;
+    const R tbase = Mo + c3 * s0, ksb = c1 + c2 * s0;
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        if (a >= nown) break;
-        const int lr = loc[a];
-        const int base = rowoff[lr];
-        int slot[4];
+    for (int b = 0; b < 4; b++) {
+        const R *gb = C.gb[b];
+        R db[4];  // d[k][b]
 #pragma unroll
-        for (int b = 0; b < 4; b++) slot[b] = base + (int)((rw[a] >> (8 * b)) & 0xffu);
+        for (int k = 0; k < 4; k++) db[k] = U[k][0] * gb[0] + U[k][1] * gb[1] + U[k][2] * gb[2];
+        const R sb = db[0] + db[1] + db[2] + db[3];
+        const R gram = dk0[0] * db[0] + dk0[1] * db[1] + dk0[2] * db[2] + dk0[3] * db[3];
+        const R K = g0[0] * gb[0] + g0[1] * gb[1] + g0[2] * gb[2];
+        R T = tbase + ksb * sb + c1 * db[0] + c3 * dk0[b] + c2 * gram + muV * K;
+        if (b == 0) T += Mo;
+        C.T[b] = T;
+        C.K[b] = K;
+        C.s[b] = sb;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        C.gm[c] = muV * g0[c];
+        C.gt[c] = t2V * g0[c];
+        C.gmt[c] = C.gm[c] + C.gt[c];
+        C.pa[c] = -v4 * g0[c];
+        C.tg[c] = t1 * g0[c];
+    }
+    C.qa = t1rho * v4 * s0;
+    C.v4 = v4;
+    C.t1V = t1 * V;
+    C.rv4 = rho * v4;
+    C.dv4 = rdt * v4;
+}
+
+// acc (+)= block (0, b) of the element: FRESH overwrites, otherwise adds (FP64: folded into the
+// multiply-adds; mixed: each FP32 value converted, then added in FP64).
+template <typename R, bool FRESH>
+__device__ __forceinline__ void block0(const Row0<R> &C, int b, double acc[16]) {
+    const R *gb = C.gb[b];
+    const R T = C.T[b], K = C.K[b];
+    const R rbb = C.rv4 * C.s[b] + C.dv4;
+    if constexpr (std::is_same<R, double>::value) {
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int cp = 0; cp < 3; cp++) {
+                double &a = acc[4 * c + cp];
+                if (c == cp)
+                    a = FRESH ? fma(gb[c], C.gmt[c], T) : fma(gb[c], C.gmt[c], a) + T;
+                else
+                    a = FRESH ? fma(C.gm[cp], gb[c], C.gt[c] * gb[cp]) : fma(C.gt[c], gb[cp], fma(C.gm[cp], gb[c], a));
+            }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            double &u = acc[4 * c + 3];
+            u = FRESH ? fma(C.qa, gb[c], C.pa[c]) : fma(C.qa, gb[c], u) + C.pa[c];
+            double &p = acc[12 + c];
+            p = FRESH ? fma(C.v4, gb[c], C.tg[c] * rbb) : fma(C.tg[c], rbb, fma(C.v4, gb[c], p));
+        }
+        acc[15] = FRESH ? C.t1V * K : fma(C.t1V, K, acc[15]);
+    } else {
+        R v[16];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int cp = 0; cp < 3; cp++)
+                v[4 * c + cp] = (c == cp) ? gb[c] * C.gmt[c] + T : C.gm[cp] * gb[c] + C.gt[c] * gb[cp];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            v[4 * c + 3] = C.pa[c] + C.qa * gb[c];
+            v[12 + c] = C.v4 * gb[c] + C.tg[c] * rbb;
+        }
+        v[15] = C.t1V * K;
+#pragma unroll
+        for (int i = 0; i < 16; i++) acc[i] = FRESH ? (double)v[i] : acc[i] + (double)v[i];
+    }
+}
+
+// One run (RunRec as two uint4: h = row, hinge, k0, len, diag, jslot, last, pad; k = knew[4],
+// kslot[4]). Element q of the run has the vertices (row, hinge, k_old(q), k_new(q)); only row `row`
+// (local vertex 0) is integrated. The lane sums in FP64 registers the diagonal block and the RHS
+// row (every element of the run adds to them), the block (row, hinge) (likewise) and the block
+// (row, k_new(q)), which element q+1 adds to again as its (row, k_old); that sum is complete after
+// element q+1 and goes into the LDS image then. Per element one block is added into LDS, per run
+// three blocks and the RHS row. Node data are read from the LDS node table for every element.
+template <typename R>
+__device__ __forceinline__ void tile_run(const TileArgs &A, const uint4 h, const uint4 k, double *acc, double *racc,
+                                         const double *nodes) {
+    const int row = (int)(h.x & 0xffffu), hinge = (int)(h.x >> 16);
+    const int len = (int)(h.y >> 16);
+    const int dslot = (int)(h.z & 0xffffu), jslot = (int)(h.z >> 16), last = (int)(h.w & 0xffffu);
+    double sd[16], sj[16], sa[16], sr[4];
+#pragma unroll
+    for (int i = 0; i < 16; i++) sd[i] = sj[i] = sa[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) sr[c] = 0.0;
+    int kold = (int)(h.y & 0xffffu);
+    for (int q = 0; q < len; q++) {
+        const int sh = (q & 1) * 16;
+        const int kn = (int)(((q < 2 ? k.x : k.y) >> sh) & 0xffffu);
+        const int ks = (int)(((q < 2 ? k.z : k.w) >> sh) & 0xffffu);
+        Row0<R> C;
         R rb[4];
-        element_row<R>(E, a, rb, [&](int b, const R *blk) {
-            double *q = acc + kBlkStride * slot[b];
+        {
+            double X[4][3], U[4][3];
+            node_load(nodes, row, X[0], U[0]);
+            node_load(nodes, hinge, X[1], U[1]);
+            node_load(nodes, kold, X[2], U[2]);
+            node_load(nodes, kn, X[3], U[3]);
+            Geo2 g;
+            geometry2(X, g);
+            row0_setup<R>(g, U, A.rho, A.mu, A.dt, C, rb);
+        }
 #pragma unroll
-            for (int i = 0; i < 16; i++) lds_add(q + i, (double)blk[i]);
-        });
-        double *q = racc + kRhsStride * lr;
-#pragma unroll
-        for (int c = 0; c < 4; c++) lds_add(q + c, (double)rb[c]);
+        for (int c = 0; c < 4; c++) sr[c] += (double)rb[c];
+        block0<R, false>(C, 0, sd);
+        block0<R, false>(C, 1, sj);
+        block0<R, false>(C, 2, sa);
+        lds_add16(acc + kBlkStride * ks, sa);
+        block0<R, true>(C, 3, sa);
+        kold = kn;
     }
+    lds_add16(acc + kBlkStride * last, sa);
+    lds_add16(acc + kBlkStride * jslot, sj);
+    lds_add16(acc + kBlkStride * dslot, sd);
+    double *r = racc + kRhsStride * row;
+#pragma unroll
+    for (int c = 0; c < 4; c++) lds_add(r + c, sr[c]);
 }
 
 // One tile from prologue to write-out. Ends with a barrier so that the caller may start the next
@@ -484,16 +624,18 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     const int nblk = (int)(A.tile_b0[tile + 1] - b0);
     const int nnod = (int)(A.tile_nptr[tile + 1] - A.tile_nptr[tile]);
     // block image at a padded stride (a block's 16 values sit at immediate offsets from one base and
-    // neighbouring slots start on different banks), RHS rows, node table, row offsets
+    // neighbouring slots start on different banks), RHS rows, node table
     double *acc = smem;
     double *racc = smem + lds_racc_off(nblk);
     double *nodes = smem + lds_nodes_off(nblk, nrows);
-    int *rowoff = reinterpret_cast<int *>(smem + lds_rowoff_off(nblk, nrows, nnod));
-    const int64_t p0 = A.tile_eptr[tile], p1 = A.tile_eptr[tile + 1];
-    // issue the first element record and the node gathers before the LDS clears and the barrier
-    Rec cur{};
+    const int64_t p0 = A.tile_rptr[tile], p1 = A.tile_rptr[tile + 1];
+    // issue the first run record and the node gathers before the LDS clears and the barrier
     int64_t p = p0 + tid;
-    if (p < p1) cur = load_rec(A, p);
+    uint4 h = make_uint4(0u, 0u, 0u, 0u), kk = h;
+    if (p < p1) {
+        h = A.runs[2 * p];
+        kk = A.runs[2 * p + 1];
+    }
     if (first && tid < nnod) {
         double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * tid);
         nd[0] = make_double2(c1.x, c1.y);
@@ -509,7 +651,6 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
         nd[1] = make_double2(c.z, v[0]);
         nd[2] = make_double2(v[1], v[2]);
     }
-    for (int i = tid; i < nrows; i += NT) rowoff[i] = (int)(A.bptr[r0 + i] - b0);
     {
         double2 *a2 = reinterpret_cast<double2 *>(acc);
         const int n2 = (kBlkStride * nblk + 1) >> 1;
@@ -517,14 +658,14 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     }
     for (int i = tid; i < kRhsStride * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();
-    // one record ahead: the next element's record is in flight while this one is integrated
+    // one run per lane (a tile with more runs than lanes takes several rounds)
     while (p < p1) {
-        const int64_t pn = p + NT;
-        Rec nxt{};
-        if (pn < p1) nxt = load_rec(A, pn);
-        tile_element<R>(A, cur, nrows, acc, racc, nodes, rowoff);
-        cur = nxt;
-        p = pn;
+        tile_run<R>(A, h, kk, acc, racc, nodes);
+        p += NT;
+        if (p < p1) {
+            h = A.runs[2 * p];
+            kk = A.runs[2 * p + 1];
+        }
     }
     __syncthreads();
     // write the image out: block k, value pair j -> values[(b0 + k) * 16 + 2j]
@@ -726,7 +867,7 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
 }  // namespace
 
 size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
-    return (size_t)lds_rowoff_off(cap_blocks, cap_rows, cap_nodes) * 8 + (size_t)cap_rows * 4;
+    return (size_t)lds_tile_doubles(cap_blocks, cap_rows, cap_nodes) * 8;
 }
 
 // Raise a kernel's dynamic-LDS limit once (not at every launch, so launches can be captured).

@@ -43,8 +43,8 @@ class Options(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [("npoin", C.c_int64), ("nelem", C.c_int64), ("nnzb", C.c_int64), ("ncolours", C.c_int32),
                 ("uploaded", C.c_int32), ("ws_bytes", C.c_size_t), ("max_row_blocks", C.c_int64),
-                ("ntiles", C.c_int64 * 2), ("tile_elems", C.c_int64 * 2), ("tile_blocks", C.c_int32 * 2),
-                ("tile_threads", C.c_int32 * 2), ("tile_max_colours", C.c_int32 * 2),
+                ("ntiles", C.c_int64 * 2), ("tile_runs", C.c_int64 * 2), ("tile_blocks", C.c_int32 * 2),
+                ("tile_threads", C.c_int32 * 2), ("tile_max_runs", C.c_int32 * 2),
                 ("tile_lds_bytes", C.c_int32 * 2), ("gather_ntiles", C.c_int64), ("gather_records", C.c_int64),
                 ("gather_pairs", C.c_int64), ("gather_tile_blocks", C.c_int32), ("gather_threads", C.c_int32),
                 ("gather_lds_bytes", C.c_int32 * 2), ("residual_ntiles", C.c_int64),
@@ -78,7 +78,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
     lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
-    lib.nsa_mesh_get_tiles.argtypes = [P, i32, P, P, P, P, P, P, P]
+    lib.nsa_mesh_get_tiles.argtypes = [P, i32, P, P, P, P, P, P]
     lib.nsa_mesh_get_gather.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
     lib.nsa_mesh_release_host.argtypes = [P]
@@ -227,22 +227,25 @@ class Mesh:
         _check(load().nsa_mesh_get_colouring(self._h, _ptr(cptr), _ptr(celems)), "nsa_mesh_get_colouring")
         return cptr, celems
 
+    RUN_DTYPE = np.dtype([("row", np.uint16), ("hinge", np.uint16), ("k0", np.uint16), ("len", np.uint16),
+                          ("diag", np.uint16), ("jslot", np.uint16), ("last", np.uint16), ("pad", np.uint16),
+                          ("knew", np.uint16, (4,)), ("kslot", np.uint16, (4,))])
+
     def tiles(self, scatter: int = ATOMIC):
-        """Row-tile plan of one scatter mode: dict of tile_row, tile_eptr, elems, colours, tile_nptr,
-        tile_nodes and records (structured: loc uint16[4], rank uint8[4][4])."""
+        """Row-tile plan of one scatter mode: dict of tile_row, tile_rptr, run_elems (int32 [runs][4]),
+        tile_nptr, tile_nodes and runs (structured, RUN_DTYPE)."""
         i = self.info
-        nt, ne = i.ntiles[scatter], i.tile_elems[scatter]
-        rec_dt = np.dtype([("loc", np.uint16, (4,)), ("rank", np.uint8, (4, 4))])
-        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_eptr=np.zeros(nt + 1, np.int64),
-                   elems=np.zeros(ne, np.int32), colours=np.zeros(ne, np.int32), tile_nptr=np.zeros(nt + 1, np.int64),
-                   records=np.zeros(ne, rec_dt))
+        nt, nr = i.ntiles[scatter], i.tile_runs[scatter]
+        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_rptr=np.zeros(nt + 1, np.int64),
+                   run_elems=np.zeros((nr, 4), np.int32), tile_nptr=np.zeros(nt + 1, np.int64),
+                   runs=np.zeros(nr, self.RUN_DTYPE))
         lib = load()
-        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), None, None, None, None, _ptr(out["tile_nptr"]), None,
-                                      None), "nsa_mesh_get_tiles")
+        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), None, None, None, _ptr(out["tile_nptr"]), None, None),
+               "nsa_mesh_get_tiles")
         out["tile_nodes"] = np.zeros(int(out["tile_nptr"][-1]), np.int32)
-        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), _ptr(out["tile_row"]), _ptr(out["tile_eptr"]),
-                                      _ptr(out["elems"]), _ptr(out["colours"]), None, _ptr(out["tile_nodes"]),
-                                      _ptr(out["records"])), "nsa_mesh_get_tiles")
+        _check(lib.nsa_mesh_get_tiles(self._h, int(scatter), _ptr(out["tile_row"]), _ptr(out["tile_rptr"]),
+                                      _ptr(out["run_elems"]), None, _ptr(out["tile_nodes"]), _ptr(out["runs"])),
+               "nsa_mesh_get_tiles")
         return out
 
     def gather(self):

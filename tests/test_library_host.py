@@ -136,62 +136,71 @@ def test_isolated_nodes_match_oracle(lib):
     assert mb[11] == mb[10]
 
 
-def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024, overflow_colour=None):
-    """Every index the tiled kernel derives from the plan stays inside its buffers, and the record
-    order is the one the mode relies on."""
+def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
+    """Every index the tiled kernel derives from the plan stays inside its buffers, and the runs are
+    what the kernel assumes: every (element, owned row) pair of a tile in exactly one run, element q
+    of a run made of (row, hinge, k_old(q), k_new(q)) with k_old chained from k_new, and every slot
+    the block of (row, column) inside the tile."""
     info = mesh.info
     t = mesh.tiles(scatter)
     bptr, bcol, emap = mesh.pattern()
-    tr, te = t["tile_row"], t["tile_eptr"]
+    tr, tp = t["tile_row"], t["tile_rptr"]
     assert tr[0] == 0 and tr[-1] == m.npoin and np.all(np.diff(tr) > 0)
     nblk = bptr[tr[1:]] - bptr[tr[:-1]]
     nrows = np.diff(tr)
     nnod = np.diff(t["tile_nptr"])
-    need = [((17 * b + 5 * r + 1) // 2 * 2 + 6 * n) * 8 + 4 * r for b, r, n in zip(nblk, nrows, nnod)]
+    need = [((17 * b + 5 * r + 1) // 2 * 2 + 6 * n) * 8 for b, r, n in zip(nblk, nrows, nnod)]
     assert info.tile_lds_bytes[scatter] == max(need) <= lds_limit, "LDS allocation must cover the largest tile"
     assert max(need) <= max(info.tile_blocks[scatter] * 160, need[int(np.argmax(nblk))])
-    ranks = emap - bptr[m.lnods][:, :, None]
-    assert ranks.max() < 256
+    assert tp[0] == 0 and tp[-1] == info.tile_runs[scatter] and np.all(np.diff(tp) >= 0)
+    assert info.tile_max_runs[scatter] == np.diff(tp).max()
     n2e = [[] for _ in range(m.npoin)]
     for e, nodes in enumerate(m.lnods):
         for a in nodes:
             n2e[a].append(e)
+
+    def slot(i, g, r0):
+        lo, hi = bptr[i], bptr[i + 1]
+        q = lo + np.searchsorted(bcol[lo:hi], g)
+        assert q < hi and bcol[q] == g, "column not in the row's pattern"
+        return q - bptr[r0]
+
     for k in range(len(tr) - 1):
         r0, r1 = tr[k], tr[k + 1]
         nr = r1 - r0
-        els = t["elems"][te[k]:te[k + 1]]
-        cols = t["colours"][te[k]:te[k + 1]]
-        recs = t["records"][te[k]:te[k + 1]]
-        want = sorted({e for i in range(r0, r1) for e in n2e[i]})
-        assert sorted(els) == want
-        own = ((m.lnods[els] >= r0) & (m.lnods[els] < r1)).sum(axis=1)
-        assert np.all(np.diff(own) <= 0), "record order: owned-row count descending"
-        for c in np.unique(cols):
-            if c == overflow_colour:
-                continue  # the shared colour of a tile that needs more than 127
-            nodes = m.lnods[els[cols == c]].ravel()
-            owned = nodes[(nodes >= r0) & (nodes < r1)]
-            assert np.unique(owned).size == owned.size, f"tile {k} colour {c} shares an owned node"
-        # node table and records: what the kernel indexes with them
+        runs = t["runs"][tp[k]:tp[k + 1]]
+        rel = t["run_elems"][tp[k]:tp[k + 1]]
+        assert len(runs) <= info.tile_threads[scatter] or nr == 1, "one round of runs per tile"
+        lens = runs["len"].astype(int)
+        desc = np.sort(lens)[::-1]
+        for h in range(0, len(lens), 64):  # each wavefront takes the next 64 runs by length
+            assert np.array_equal(np.sort(lens[h:h + 64])[::-1], desc[h:h + 64]), "wavefronts by run length"
         nodes = t["tile_nodes"][t["tile_nptr"][k]:t["tile_nptr"][k + 1]]
         assert np.array_equal(nodes[:nr], np.arange(r0, r1))
         assert np.all(np.diff(nodes[nr:]) > 0) and not np.any((nodes[nr:] >= r0) & (nodes[nr:] < r1))
+        els = sorted({e for i in range(r0, r1) for e in n2e[i]})
         assert set(nodes.tolist()) == set(m.lnods[els].ravel().tolist())
         assert nodes.size <= 65535
-        for e, rec in zip(els, recs):
-            loc = rec["loc"].astype(np.int64)
-            assert np.all(loc < nodes.size)
-            g = nodes[loc]
-            assert sorted(g.tolist()) == sorted(m.lnods[e].tolist())
-            ow = loc < nr
-            nown = int(ow.sum())
-            assert np.all(ow[:nown]) and not np.any(ow[nown:]), "owned nodes must come first"
-            for q in range(nown):
-                row = g[q]
-                for b in range(4):
-                    rank = int(rec["rank"][q, b])
-                    assert bptr[row] + rank < bptr[row + 1] and bcol[bptr[row] + rank] == g[b]
-                    assert 0 <= bptr[row] - bptr[r0] + rank < nblk[k]
+        pairs = []
+        for r, es in zip(runs, rel):
+            L = int(r["len"])
+            assert 1 <= L <= 4 and r["pad"] == 0 and r["row"] < nr
+            assert np.all(es[L:] == -1) and np.all(es[:L] >= 0)
+            for f in ("hinge", "k0"):
+                assert r[f] < nodes.size
+            assert np.all(r["knew"][:L] < nodes.size)
+            i, j = int(nodes[r["row"]]), int(nodes[r["hinge"]])
+            kold = int(nodes[r["k0"]])
+            for q in range(L):
+                kn = int(nodes[r["knew"][q]])
+                assert sorted(m.lnods[es[q]].tolist()) == sorted([i, j, kold, kn]), "element vertices"
+                assert r["kslot"][q] == slot(i, kold, r0)
+                pairs.append((int(es[q]), i))
+                kold = kn
+            assert r["diag"] == slot(i, i, r0) and r["jslot"] == slot(i, j, r0) and r["last"] == slot(i, kold, r0)
+            assert max(r["diag"], r["jslot"], r["last"], *r["kslot"][:L]) < nblk[k]
+        want = sorted((e, i) for i in range(r0, r1) for e in n2e[i])
+        assert sorted(pairs) == want, "every (element, owned row) pair in exactly one run"
 
 
 @pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
@@ -363,7 +372,8 @@ def test_residual_plan_in_bounds(lib, rows):
 def test_high_degree_hub(lib, level):
     """A node in 128 / 512 / 2048 elements (rows of 67 / 259 / 1027 blocks): the global colouring
     grows past 128 colours and stays valid; rows over 256 blocks leave the mesh without row tiles
-    (the direct kernel serves it), a tile that needs more than 127 colours shares its last one."""
+    (the direct kernel serves it); the hub's row needs more runs than a workgroup has lanes and
+    takes a tile of its own."""
     m = inputs.hub_mesh(level, seed=level)
     mesh = nsa.Mesh.from_inputs(m, tile_rows_residual=64)
     info = mesh.info
@@ -380,7 +390,6 @@ def test_high_degree_hub(lib, level):
         assert list(info.ntiles) == [0, 0]
     else:
         for scatter in (nsa.ATOMIC, nsa.COLOUR):
-            assert info.tile_max_colours[scatter] <= 128
-            check_tile_plan(m, mesh, scatter, overflow_colour=127)
+            check_tile_plan(m, mesh, scatter)
     assert info.residual_ntiles >= 1
     check_residual_plan(m, mesh)
