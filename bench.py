@@ -431,6 +431,7 @@ def main():
     ap.add_argument("--tile-rows-residual", type=int, default=256, help="rows per tile of the residual plan")
     ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
+    ap.add_argument("--tile-threads", type=int, default=0, help="workgroup size of the atomic-mode plan (0 = default)")
     ap.add_argument("--tile-blocks-colour", type=int, default=160, help="tile size of the colour-mode plan")
     ap.add_argument("--no-beside", action="store_true",
                     help="skip timing the other precision beside (mixed beside FP64, or FP64 beside mixed)")
@@ -486,7 +487,8 @@ def main():
     mesh = nsa.Mesh.from_inputs(m, tile_blocks=0 if gather else args.tile_blocks,
                                 tile_blocks_colour=0 if gather else args.tile_blocks_colour,
                                 tile_blocks_gather=args.tile_blocks_gather if gather else 0,
-                                keep_direct=kern in (nsa.KERNEL_DIRECT, nsa.KERNEL_AUTO))
+                                keep_direct=kern in (nsa.KERNEL_DIRECT, nsa.KERNEL_AUTO),
+                                tile_threads=args.tile_threads or None)
     mesh.upload("cuda:0")
     info = mesh.info
     if gather:

@@ -85,7 +85,8 @@ typedef struct nsa_options {
     int32_t accumulate;        /* 0: values/rhs are overwritten; 1: contributions are added to
                                   what the arrays hold (the inout semantics of Listing 2) */
     int32_t block_threads;     /* threads per workgroup, 0 = default; direct kernel: 64..256 in
-                                  steps of 64; tiled atomic mode: 64, 128 or 256 (default 256);
+                                  steps of 64; tiled atomic mode: 64, 128, 192 or 256 (default:
+                                  the plan's, see nsa_mesh_set_tile_threads);
                                   ignored by the tiled colour mode (one wavefront per tile) */
     int32_t kernel;            /* NSA_KERNEL_AUTO, _TILED, _DIRECT or _GATHER */
     int32_t reserved[3];       /* must be zero */
@@ -175,6 +176,10 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
  * With scatter = NSA_RESIDUAL_PLAN it sizes the plan of nsa_assemble_residual, also built only when
  * asked for: contiguous row ranges of at most tile_blocks rows (1..4096; 0 drops the plan) whose LDS
  * (48 bytes per touched node, 40 per row) stays within 64 KB. */
+/* Workgroup size of the throughput (NSA_ATOMIC) tile plan: 64, 128, 192 or 256 threads (default 256).
+ * A tile then holds at most that many runs (one per lane), so the size also bounds the tile. Before
+ * nsa_mesh_upload (NSA_ESTATE after). The deterministic plan always uses one wavefront per tile. */
+nsa_status nsa_mesh_set_tile_threads(nsa_mesh *m, int32_t threads);
 /* Whether nsa_mesh_upload also stores the direct kernel's arrays (SoA connectivity, element-to-block
  * map and their colour-ordered copies, ~160 bytes per element; default 1). With 0 the mesh can only
  * be assembled by the tiled kernel (NSA_KERNEL_DIRECT returns NSA_EUNSUPPORTED). Before upload. */

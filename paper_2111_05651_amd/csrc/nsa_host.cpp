@@ -1043,7 +1043,7 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
     try {
         for (int k = 0; k < 2; k++) {
             if (m->want_blocks[k] > 0) {
-                nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], kPlanThreads[k]);
+                nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], k == 0 ? m->want_threads : kPlanThreads[k]);
                 if (st) return st;
             } else {
                 m->plan[k] = nsa::TilePlan();
@@ -1230,6 +1230,18 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
     }
     if (m->want_blocks[scatter] != tile_blocks || !m->planned) {
         m->want_blocks[scatter] = tile_blocks;
+        m->planned = false;
+    }
+    return ok();
+}
+
+nsa_status nsa_mesh_set_tile_threads(nsa_mesh *m, int32_t threads) {
+    if (!m || (threads != 64 && threads != 128 && threads != 192 && threads != 256))
+        return fail(NSA_EINVAL, "nsa_mesh_set_tile_threads: threads must be 64, 128, 192 or 256");
+    if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tile_threads after upload");
+    std::lock_guard<std::mutex> g(m->plan_mu);
+    if (m->want_threads != threads) {
+        m->want_threads = threads;
         m->planned = false;
     }
     return ok();
@@ -1910,7 +1922,8 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     if (dev != b->device) return fail(NSA_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
     // the throughput plan accepts a workgroup-size override for tuning; the deterministic plan needs
     // one wavefront per tile
-    const int threads = (b->scatter == NSA_ATOMIC && (o.block_threads == 128 || o.block_threads == 256))
+    const int threads = (b->scatter == NSA_ATOMIC && (o.block_threads == 128 || o.block_threads == 192 ||
+                                                       o.block_threads == 256))
                             ? o.block_threads : b->threads;
     st = hip_check(nsa::launch_tiled_batch(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64,
                                            (const nsa::TileArgs *)(b->ws + b->r_desc.off),

@@ -265,6 +265,7 @@ struct nsa_mesh {
     // need (info, tiles, upload) from the requested sizes (0 = no plan for that mode)
     nsa::TilePlan plan[2];
     int32_t want_blocks[2] = {0, 0};
+    int32_t want_threads = 256;         // workgroup size of the throughput plan
     nsa::GatherPlan gplan;              // gather tiles (both scatter modes, both precisions)
     int32_t want_gather = 0;
     nsa::ResPlan rplan;                 // residual tiles (explicit-residual outputs)

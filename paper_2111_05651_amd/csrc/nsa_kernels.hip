@@ -885,7 +885,7 @@ hipError_t ensure_lds(const void *kern, size_t bytes) {
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     const size_t lds = (size_t)a.lds_bytes;
-    const int nt = (a.threads == 64 || a.threads == 128) ? a.threads : 256;
+    const int nt = (a.threads == 64 || a.threads == 128 || a.threads == 192) ? a.threads : 256;
     const dim3 grid((unsigned)xcd_grid(a.ntiles)), block(nt);
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = ensure_lds(reinterpret_cast<const void *>(kern), lds);
@@ -896,6 +896,7 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     const bool mixed = k == TileKern::Mixed;
     if (nt == 64) return mixed ? go(k_tiled<float, 64>) : go(k_tiled<double, 64>);
     if (nt == 128) return mixed ? go(k_tiled<float, 128>) : go(k_tiled<double, 128>);
+    if (nt == 192) return mixed ? go(k_tiled<float, 192>) : go(k_tiled<double, 192>);
     return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
 }
 
@@ -918,6 +919,10 @@ hipError_t prepare_batch(int threads, size_t lds) {
                           reinterpret_cast<const void *>(k_tiled_batch<float, 64, false>),
                           reinterpret_cast<const void *>(k_tiled_batch<double, 128, false>),
                           reinterpret_cast<const void *>(k_tiled_batch<float, 128, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 192, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 192, false>),
+                          reinterpret_cast<const void *>(k_tiled_batch<double, 192, true>),
+                          reinterpret_cast<const void *>(k_tiled_batch<float, 192, true>),
                           reinterpret_cast<const void *>(k_tiled_batch<double, 256, false>),
                           reinterpret_cast<const void *>(k_tiled_batch<float, 256, false>),
                           reinterpret_cast<const void *>(k_tiled_batch<double, 64, true>),
@@ -934,7 +939,7 @@ hipError_t prepare_batch(int threads, size_t lds) {
 hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work, int64_t total, int threads,
                               int64_t lds, int grid_wgs, hipStream_t s) {
     if (total <= 0) return hipSuccess;
-    const int nt = (threads == 64 || threads == 128) ? threads : 256;
+    const int nt = (threads == 64 || threads == 128 || threads == 192) ? threads : 256;
     const int64_t items = 8 * ((total + 7) / 8);
     const bool persist = grid_wgs > 0 && grid_wgs < items;
     const dim3 grid((unsigned)(persist ? std::max(8, grid_wgs & ~7) : xcd_grid(total))), block(nt);
@@ -946,6 +951,8 @@ hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work
         if (mixed) NSA_LAUNCH_BATCH(float, 64, P); else NSA_LAUNCH_BATCH(double, 64, P);       \
     } else if (nt == 128) {                                                                     \
         if (mixed) NSA_LAUNCH_BATCH(float, 128, P); else NSA_LAUNCH_BATCH(double, 128, P);     \
+    } else if (nt == 192) {                                                                     \
+        if (mixed) NSA_LAUNCH_BATCH(float, 192, P); else NSA_LAUNCH_BATCH(double, 192, P);     \
     } else {                                                                                    \
         if (mixed) NSA_LAUNCH_BATCH(float, 256, P); else NSA_LAUNCH_BATCH(double, 256, P);     \
     }

@@ -256,6 +256,53 @@ def served_requests(nreq: int, nmesh: int, rate: float, seed: int = 6):
                  vel_seed=int(vseed[i])) for i in range(nreq)]
 
 
+def shape_quality(lnods: np.ndarray, coord: np.ndarray) -> np.ndarray:
+    """|det J| / L^3 per element, L the longest edge: 1/sqrt(2) for the regular tetrahedron's
+    |det J| = L^3 / sqrt(2), tending to 0 for slivers, needles, caps and wedges."""
+    X = coord[lnods.astype(np.int64)]
+    J = X[:, 1:, :] - X[:, :1, :]
+    det = np.abs(np.linalg.det(J))
+    edges = [np.linalg.norm(X[:, a] - X[:, b], axis=1) for a in range(4) for b in range(a + 1, 4)]
+    return det / np.max(edges, axis=0) ** 3
+
+
+def bad_element_soup(eps=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), copies: int = 8, seed: int = 7, rho: float = 1.0,
+                     mu: float = 1e-3, dt: float = 1e-2) -> Mesh:
+    """Disjoint, badly shaped tetrahedra (each with its own four nodes), for every flatness eps:
+      sliver  four near-coplanar vertices of a unit square, lifted alternately by +-eps/2;
+      needle  a base triangle of side ~eps and an apex at distance 1;
+      cap     a unit triangle and an apex eps above a point inside it;
+      wedge   two long opposite edges that nearly cross (distance eps).
+    Each shape is randomly rotated, scaled by U[0.5, 2] and translated, `copies` times per eps; the
+    velocity is U[-1,1]^3 per node. |det J| / L^3 (L the longest edge) reaches ~eps (sliver, cap,
+    wedge) and ~eps^2 (needle): 1e-2 down to 1e-12."""
+    rng = np.random.default_rng(seed)
+    tets = []
+    for e in eps:
+        shapes = [np.array([[0, 0, e / 2], [1, 0, -e / 2], [1, 1, e / 2], [0, 1, -e / 2]]),
+                  np.array([[0, 0, 0], [e, 0, 0], [0.5 * e, 0.87 * e, 0], [0.3 * e, 0.3 * e, 1.0]]),
+                  np.array([[0, 0, 0], [1, 0, 0], [0.5, 0.87, 0], [0.45, 0.3, e]]),
+                  np.array([[0, 0, 0], [1, 0, 0], [0.5, -0.5, e], [0.5, 0.5, e]])]
+        for _ in range(copies):
+            for sh in shapes:
+                q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+                tets.append((sh @ q.T) * rng.uniform(0.5, 2.0) + rng.uniform(-5.0, 5.0, size=3))
+    coord = np.concatenate(tets).astype(np.float64)
+    lnods = np.arange(coord.shape[0], dtype=np.int32).reshape(-1, 4)
+    velocity = rng.uniform(-1.0, 1.0, size=coord.shape)
+    return Mesh(n=0, lnods=lnods, coord=coord, velocity=velocity, rho=rho, mu=mu, dt=dt, name="bad_soup")
+
+
+def boundary_layer_mesh(n: int = 6, thickness: float = 1e-3, seed: int = 8, rho: float = 1.0, mu: float = 1e-3,
+                        dt: float = 1e-2) -> Mesh:
+    """A jittered Kuhn cube squashed to [0,1]^2 x [0, thickness] (the flat cells of a boundary layer):
+    every element is a connected sliver with |det J| / L^3 ~ thickness / 10; velocity U[-1,1]^3."""
+    m = make_mesh(n, jitter=True, velocity="uniform", seed=seed, rho=rho, mu=mu, dt=dt)
+    coord = m.coord * np.array([1.0, 1.0, thickness])
+    return Mesh(n=n, lnods=m.lnods, coord=coord, velocity=m.velocity, rho=rho, mu=mu, dt=dt,
+                name=f"layer{n}_{thickness:g}")
+
+
 def hub_mesh(level: int = 4, seed: int = 0, rho: float = 1.0, mu: float = 1e-3, dt: float = 1e-2) -> Mesh:
     """A fan of tets around one hub node: the octahedron's faces split `level` times into four,
     pushed to the unit sphere, each surface triangle joined to the centre. The hub's block row has

@@ -23,7 +23,7 @@ RESIDUAL_PLAN = 3
 
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
-           "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
+           "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_set_tile_threads", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
            "nsa_assemble_batched", "nsa_fill_uniform", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_pattern_fill.argtypes = [i64, i64, P, P, P, P]
     lib.nsa_mesh_create.argtypes = [i64, i64, P, P, C.POINTER(P)]
     lib.nsa_mesh_set_tiling.argtypes = [P, i32, i32]
+    lib.nsa_mesh_set_tile_threads.argtypes = [P, i32]
     lib.nsa_mesh_keep_direct.argtypes = [P, i32]
     lib.nsa_mesh_destroy.argtypes = [P]
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
@@ -158,7 +159,8 @@ class Mesh:
 
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
                  tile_blocks_colour: int | None = None, keep_direct: bool = True,
-                 tile_blocks_gather: int | None = None, tile_rows_residual: int | None = None):
+                 tile_blocks_gather: int | None = None, tile_rows_residual: int | None = None,
+                 tile_threads: int | None = None):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -172,6 +174,8 @@ class Mesh:
             _check(lib.nsa_mesh_set_tiling(h, ATOMIC, int(tile_blocks)), "nsa_mesh_set_tiling")
         if tile_blocks_colour is not None:
             _check(lib.nsa_mesh_set_tiling(h, COLOUR, int(tile_blocks_colour)), "nsa_mesh_set_tiling")
+        if tile_threads is not None:
+            _check(lib.nsa_mesh_set_tile_threads(h, int(tile_threads)), "nsa_mesh_set_tile_threads")
         if tile_blocks_gather is not None:
             _check(lib.nsa_mesh_set_tiling(h, GATHER_PLAN, int(tile_blocks_gather)), "nsa_mesh_set_tiling")
         if tile_rows_residual is not None:
@@ -183,9 +187,9 @@ class Mesh:
     @classmethod
     def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None,
                     tile_blocks_gather: int | None = None, keep_direct: bool = True,
-                    tile_rows_residual: int | None = None) -> "Mesh":
+                    tile_rows_residual: int | None = None, tile_threads: int | None = None) -> "Mesh":
         return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather,
-                   tile_rows_residual)
+                   tile_rows_residual, tile_threads)
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")

@@ -467,7 +467,41 @@ def pin_residual_lumped(lib, n=3, seed=25):
     _close(dt_rho, w, 0, 1e-14 * w.max(), "tau-weighted lumped mass")
 
 
+def pin_assemble_rows(lib):
+    """The row-by-row route (used to check meshes too large to assemble whole) against the whole-mesh
+    route: for every row of small jittered / permuted / RCM meshes, a mesh with nodes in no element
+    and a hub node in 128 elements, and for a sample of the rows of a larger one, the rebuilt
+    column set equals the row of the set-based pattern and the summed blocks and RHS are bit-for-bit
+    those of the whole-mesh assembly (same element values, same element order)."""
+    meshes = [inputs.make_mesh(3, jitter=True, permute=True, velocity="vortex", seed=41),
+              inputs.make_mesh(4, jitter=True, permute=True, rcm=True, sort_elements=True, seed=42),
+              inputs.hub_mesh(2, seed=43)]
+    iso = inputs.make_mesh(2, jitter=True, seed=44)
+    ln = iso.lnods.copy()
+    ln[ln >= 5] += 2   # nodes 5 and 6 in no element
+    coord = np.vstack([iso.coord[:5], [[3.0, 3, 3], [4.0, 4, 4]], iso.coord[5:]])
+    vel = np.vstack([iso.velocity[:5], [[1.0, 2, 3], [4.0, 5, 6]], iso.velocity[5:]])
+    meshes.append(inputs.Mesh(n=2, lnods=ln, coord=coord, velocity=vel, rho=iso.rho, mu=iso.mu, dt=iso.dt))
+    big = inputs.make_mesh(8, jitter=True, permute=True, velocity="vortex", seed=45)
+    rng = np.random.default_rng(46)
+    cases = [(m, np.arange(m.npoin)) for m in meshes]
+    cases.append((big, np.unique(np.concatenate([rng.choice(big.npoin, 60, replace=False), [0, big.npoin - 1]]))))
+    for m, rows in cases:
+        bptr, bcol, emap = oracle.pattern(m.npoin, m.lnods, lib=lib)
+        values, rhs = oracle.assemble(m, (bptr, bcol, emap), lib=lib)
+        maxdeg = int(np.diff(bptr).max())
+        cols, deg, vals, rr = oracle.assemble_rows(m, rows, maxdeg=maxdeg, lib=lib)
+        for s, i in enumerate(rows):
+            lo, hi = bptr[i], bptr[i + 1]
+            assert deg[s] == hi - lo, f"row {i}: {deg[s]} columns, pattern has {hi - lo}"
+            assert np.array_equal(cols[s, :deg[s]], bcol[lo:hi]), f"row {i} columns"
+            assert np.all(cols[s, deg[s]:] == -1)
+            assert np.array_equal(vals[s, :deg[s]], values[lo:hi]), f"row {i} blocks"
+            assert not np.any(vals[s, deg[s]:]), f"row {i} padding"
+            assert np.array_equal(rr[s], rhs[i]), f"row {i} RHS"
+
+
 ALL_PINS = [pin_golden, pin_geometry, pin_integrals_exact, pin_integrals_gm, pin_element_invariants,
             pin_viscous_kernel, pin_rotation_translation, pin_pattern, pin_kuhn_stencil,
             pin_divergence_theorem, pin_renumbering, pin_residual_uniform_flow, pin_residual_csr_route,
-            pin_residual_lumped]
+            pin_residual_lumped, pin_assemble_rows]

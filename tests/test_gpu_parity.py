@@ -201,32 +201,6 @@ def test_cube64_full(scatter):
             say(f"[parity] cube64 errors {err}")
 
 
-@pytest.mark.parametrize("precision", [nsa.FP64, nsa.MIXED])
-def test_cube128_sampled(precision):
-    """The 128^3 workload (12,582,912 tets) in the launch configuration the benchmark times
-    (tiled kernel, 512-block tiles, atomic scatter): sampled rows against the oracle computed row by
-    row, plus the colour path on the same rows."""
-    m = inputs.config_128()
-    say(f"[parity] cube128 nelem={m.nelem} precision={precision}")
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512, tile_blocks_gather=320).upload()
-    rng = np.random.default_rng(128)
-    rows = np.unique(np.concatenate([rng.choice(m.npoin, 190, replace=False), [0, 1, m.npoin - 2, m.npoin - 1]]))
-    cols, deg, ov, orr = oracle.assemble_rows(m, rows, maxdeg=64)
-    bptr, bcol, _ = mesh.pattern()
-    for scatter, kernel in ((nsa.ATOMIC, nsa.KERNEL_TILED), (nsa.COLOUR, nsa.KERNEL_TILED),
-                           (nsa.ATOMIC, nsa.KERNEL_GATHER)):
-        v, r = gpu_assemble(mesh, m, precision, scatter, kernel=kernel)
-        got, ref = [], []
-        for s, i in enumerate(rows):
-            lo, hi = bptr[i], bptr[i + 1]
-            assert np.array_equal(bcol[lo:hi], cols[s, :deg[s]]), f"pattern row {i}"
-            got.append(v[lo:hi])
-            ref.append(ov[s, :deg[s]])
-        err = assert_parity(np.concatenate(got), np.concatenate(ref), r[rows], orr, tol_of(precision),
-                            f"cube128 sampled precision={precision} scatter={scatter} kernel={kernel}")
-        say(f"[parity] cube128 sampled errors {err}")
-
-
 def device_class_errors(v, ref_v, r, ref_r):
     """The parity metric of tests/parity.py (per class max |got - ref| / max |ref|) on device tensors."""
     v, ref_v, r, ref_r = v.view(-1, 4, 4), ref_v.view(-1, 4, 4), r.view(-1, 4), ref_r.view(-1, 4)
@@ -239,14 +213,23 @@ def device_class_errors(v, ref_v, r, ref_r):
     return out
 
 
-def test_cube128_whole_mesh_consistency():
-    """Every entry of the 128^3 result (509M values), beyond the sampled rows the oracle computes: the
-    benchmark's launch (tiled, atomic, FP64), the tiled deterministic plan and the direct kernel
-    with its global colour classes agree to the FP64 bar everywhere; the mixed form stays within its
-    bar everywhere; the deterministic plan repeats bit for bit."""
+def test_cube128_whole_mesh():
+    """The 128^3 workload (12,582,912 tets, 509M matrix values) element by element against the
+    oracle, which assembles the whole mesh (set-based pattern, Gauss-rule element pipeline): the
+    pattern and element-to-block map bit-exact; the benchmark's launch (tiled kernel, 512-block
+    tiles, atomic scatter) and the deterministic tiled plan in both precisions, the direct kernel with
+    its global colour classes and the gather kernel, every entry within the bar of its precision;
+    the deterministic plan repeats bit for bit."""
     m = inputs.config_128()
-    say(f"[parity] cube128 whole mesh nelem={m.nelem}")
-    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512).upload()
+    say(f"[parity] cube128 whole mesh nelem={m.nelem}: oracle pattern and assembly ...")
+    pat = oracle.pattern(m.npoin, m.lnods)
+    ref_v, ref_r = oracle.assemble(m, pat)
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=512, tile_blocks_gather=320).upload()
+    bptr, bcol, emap = mesh.pattern()
+    assert np.array_equal(bptr, pat[0]) and np.array_equal(bcol, pat[1]) and np.array_equal(emap, pat[2])
+    del pat, bcol, emap
+    ref_v = torch.from_numpy(ref_v).cuda()
+    ref_r = torch.from_numpy(ref_r).cuda()
     vel = torch.from_numpy(m.velocity).cuda()
 
     def run(precision, scatter, kernel):
@@ -254,20 +237,23 @@ def test_cube128_whole_mesh_consistency():
         torch.cuda.synchronize()
         return out
 
-    ref_v, ref_r = run(nsa.FP64, nsa.ATOMIC, nsa.KERNEL_TILED)
-    for name, (prec, scat, kern), tol in (("tiled deterministic", (nsa.FP64, nsa.COLOUR, nsa.KERNEL_TILED), TOL_FP64),
-                                          ("direct colour classes", (nsa.FP64, nsa.COLOUR, nsa.KERNEL_DIRECT), TOL_FP64),
-                                          ("mixed", (nsa.MIXED, nsa.ATOMIC, nsa.KERNEL_TILED), TOL_MIXED)):
-        v, r = run(prec, scat, kern)
-        err = device_class_errors(v, ref_v, r, ref_r)
-        say(f"[parity] cube128 whole mesh {name}: {err}")
-        assert max(err.values()) <= tol, (name, err)
-        if name == "tiled deterministic":
-            v2, r2 = run(prec, scat, kern)
-            assert torch.equal(v, v2) and torch.equal(r, r2), "deterministic plan: bitwise repeat"
-            del v2, r2
-        del v, r
-        torch.cuda.empty_cache()
+    cases = [("tiled atomic", nsa.ATOMIC, nsa.KERNEL_TILED), ("tiled deterministic", nsa.COLOUR, nsa.KERNEL_TILED),
+             ("gather", nsa.ATOMIC, nsa.KERNEL_GATHER), ("direct colour classes", nsa.COLOUR, nsa.KERNEL_DIRECT)]
+    for prec in (nsa.FP64, nsa.MIXED):
+        for name, scat, kern in cases:
+            if kern == nsa.KERNEL_DIRECT and prec == nsa.MIXED:
+                continue
+            say(f"[parity] cube128 whole mesh {name} precision={prec}")
+            v, r = run(prec, scat, kern)
+            err = device_class_errors(v, ref_v, r, ref_r)
+            say(f"[parity] cube128 whole mesh {name} precision={prec}: {err}")
+            assert max(err.values()) <= tol_of(prec), (name, prec, err)
+            if name == "tiled deterministic":
+                v2, r2 = run(prec, scat, kern)
+                assert torch.equal(v, v2) and torch.equal(r, r2), "deterministic plan: bitwise repeat"
+                del v2, r2
+            del v, r
+            torch.cuda.empty_cache()
 
 
 def test_gather_bitwise_independent_of_tiling_and_mode():

@@ -56,6 +56,14 @@ MUTANTS = {
     "residual_wrong_velocity_node": ("E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];", "E.elauu[4 * a + c][4 * b + cp] * E.elvel[a][cp];"),
     "lumped_tau2": ("dt_rho[ipoin] += lump * E.tau1;", "dt_rho[ipoin] += lump * E.tau2;"),
     "lumped_no_shape": ("lump += E.gpvol[g] * E.shape[g][a];", "lump += E.gpvol[g];"),
+    "rows_insert_after_equal": ("while (k < deg[s] && row[k] < col) k++;", "while (k < deg[s] && row[k] <= col) k++;"),
+    "rows_keep_duplicates": ("if (k < deg[s] && row[k] == col) continue;", "if (0) continue;"),
+    "rows_block_transposed": ("for (int cp = 0; cp < NDOFN; cp++) blk[4 * c + cp] +=",
+                              "for (int cp = 0; cp < NDOFN; cp++) blk[4 * cp + c] +="),
+    "rows_rhs_wrong_node": ("rhs_s[4 * s + c] += E.elrhs[4 * a + c];", "rhs_s[4 * s + c] += E.elrhs[4 * ((a + 1) % 4) + c];"),
+    "rows_touched_first_vertex": ("touched |= rowslot[lnods[4 * e + a]] >= 0;", "touched |= rowslot[lnods[4 * e]] >= 0;"),
+    "rows_next_block": ("double *blk = vals + 16 * ((size_t)s * maxdeg + k);",
+                        "double *blk = vals + 16 * ((size_t)s * maxdeg + k + (k + 1 < deg[s]));"),
 }
 
 DRIVER = r"""
