@@ -102,8 +102,8 @@ typedef struct nsa_mesh_info {
     int64_t ntiles[2];         /* number of tiles (0 if the mesh cannot use the tiled kernel) */
     int64_t tile_runs[2];      /* runs over all tiles (see nsa_mesh_get_tiles) */
     int32_t tile_blocks[2];    /* requested tile size (LDS budget tile_blocks * 160 bytes) */
-    int32_t tile_threads[2];   /* workgroup size of the plan (a tile holds at most this many runs,
-                                  unless one row alone has more) */
+    int32_t tile_threads[2];   /* workgroup size of the plan (a tile holds at most tile_threads - 64
+                                  runs, tile_threads for 64, unless one row alone has more) */
     int32_t tile_max_runs[2];  /* largest number of runs in one tile */
     int32_t tile_lds_bytes[2]; /* LDS a workgroup uses (largest tile) */
     /* gather plan (NSA_KERNEL_GATHER) */
@@ -177,8 +177,10 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
  * asked for: contiguous row ranges of at most tile_blocks rows (1..4096; 0 drops the plan) whose LDS
  * (48 bytes per touched node, 40 per row) stays within 64 KB. */
 /* Workgroup size of the throughput (NSA_ATOMIC) tile plan: 64, 128, 192 or 256 threads (default 256).
- * A tile then holds at most that many runs (one per lane), so the size also bounds the tile. Before
- * nsa_mesh_upload (NSA_ESTATE after). The deterministic plan always uses one wavefront per tile. */
+ * A tile then holds at most threads - 64 runs (threads for 64: one run per lane of every wavefront
+ * but the last, which only takes part in loading the tile and writing it out), so the size also
+ * bounds the tile. Before nsa_mesh_upload (NSA_ESTATE after). The deterministic plan always uses one
+ * wavefront per tile. */
 nsa_status nsa_mesh_set_tile_threads(nsa_mesh *m, int32_t threads);
 /* Whether nsa_mesh_upload also stores the direct kernel's arrays (SoA connectivity, element-to-block
  * map and their colour-ordered copies, ~160 bytes per element; default 1). With 0 the mesh can only

@@ -551,7 +551,8 @@ void run_order(const std::vector<nsa::RunRec> &runs, std::vector<int32_t> &order
 
 // Row tiles for the tiled kernel (see nsa_internal.h). A tile is a contiguous row range whose LDS
 // footprint (block image, RHS rows, node table) stays within tile_blocks * 160 bytes and whose runs
-// number at most `threads` (one run per lane; a single row with more runs takes several rounds).
+// number at most threads - 64 (threads for a one-wavefront workgroup): one run per lane, a single
+// row with more runs takes several rounds.
 // Per tile: the nodes its elements touch (the owned rows first, as local ids 0 .. nrows-1, then the
 // other nodes ascending) and the runs of its rows in the order of run_order().
 nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32_t threads) {
@@ -595,6 +596,12 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
         std::vector<GRun>().swap(v);
     }
     // grow tiles row by row; the touched nodes of a tile are the columns of its rows
+    // runs per tile: one per lane of all but the last wavefront of a multi-wavefront workgroup, which
+    // takes part only in the prologue and the write-out (with every wavefront holding runs, the last
+    // one was mostly empty at the LDS budget's tile size and still issued the full element code; as a
+    // helper it speeds up the memory phases: 128^3, 512-block tiles, 256 threads, FP64 / mixed
+    // 1.71 / 1.58 ms with runs on all four wavefronts, 1.64 / 1.49 ms with three)
+    const int64_t run_cap = threads > 64 ? threads - 64 : threads;
     std::vector<int32_t> stamp(np, -1);
     P.row.push_back(0);
     int32_t tid = 0;
@@ -606,7 +613,7 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
             const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
             const int64_t need = (int64_t)nsa::tile_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
             const int64_t nruns = row_nruns[(size_t)r1 + 1] - row_nruns[(size_t)r0];
-            if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows || nruns > threads)) break;
+            if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows || nruns > run_cap)) break;
             for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
             nodes += add;
             r1++;

@@ -170,7 +170,8 @@ def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
         nr = r1 - r0
         runs = t["runs"][tp[k]:tp[k + 1]]
         rel = t["run_elems"][tp[k]:tp[k + 1]]
-        assert len(runs) <= info.tile_threads[scatter] or nr == 1, "one round of runs per tile"
+        nt = info.tile_threads[scatter]
+        assert len(runs) <= (nt - 64 if nt > 64 else nt) or nr == 1, "one round of runs per tile, last wavefront free"
         lens = runs["len"].astype(int)
         desc = np.sort(lens)[::-1]
         for h in range(0, len(lens), 64):  # each wavefront takes the next 64 runs by length
@@ -201,6 +202,19 @@ def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
             assert max(r["diag"], r["jslot"], r["last"], *r["kslot"][:L]) < nblk[k]
         want = sorted((e, i) for i in range(r0, r1) for e in n2e[i])
         assert sorted(pairs) == want, "every (element, owned row) pair in exactly one run"
+
+
+@pytest.mark.parametrize("threads", [64, 128, 192, 256])
+def test_tile_threads(lib, threads):
+    """The throughput plan for each workgroup size: every tile within threads - 64 runs (threads for
+    one wavefront) and in bounds; other sizes refused."""
+    m = inputs.make_mesh(6, jitter=True, permute=True, rcm=True, sort_elements=True, seed=33)
+    mesh = nsa.Mesh.from_inputs(m, tile_threads=threads)
+    assert mesh.info.tile_threads[0] == threads and mesh.info.tile_threads[1] == 64
+    assert mesh.info.tile_max_runs[0] <= (threads - 64 if threads > 64 else threads)
+    check_tile_plan(m, mesh, nsa.ATOMIC)
+    with pytest.raises(nsa.NsaError):
+        nsa.Mesh.from_inputs(m, tile_threads=96)
 
 
 @pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
