@@ -61,9 +61,15 @@ typedef int32_t nsa_status;
 #define NSA_ATOMIC 0           /* FP64 atomic adds from concurrent threads (throughput mode; the
                                   order of the additions, hence the last bits, may vary by run) */
 #define NSA_COLOUR 1           /* deterministic, bit-reproducible: the tiled kernel processes each
-                                  tile's elements in the plan's fixed order inside a single
-                                  wavefront; the direct kernel runs one global colour class at a
-                                  time with plain load-add-store */
+                                  tile's runs in the plan's fixed order inside a single wavefront, so
+                                  the adds into each LDS word come in program order; where two lanes
+                                  of one add instruction hit the same word (runs of one row in a
+                                  tile of fewer rows than lanes), the reproducibility rests on the
+                                  LDS applying an instruction's lanes in a fixed order, which the
+                                  tests check run to run but AMD does not document. The direct
+                                  kernel (NSA_KERNEL_DIRECT) runs one global colour class at a time
+                                  with plain load-add-store and needs no such assumption, as does
+                                  the gather kernel (NSA_KERNEL_GATHER) */
 
 /* kernel family */
 #define NSA_KERNEL_AUTO 0      /* the row-tiled kernel when the mesh allows it, else the direct one */
@@ -192,6 +198,15 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info);
  * [npoin+1], bcol [nnzb], emap [nelem][4][4]; any of them may be NULL). Requires the host copy
  * (see nsa_mesh_release_host). */
 nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol, int32_t *emap);
+/* Scalar CSR view of the block pattern (Listing 2's scatter target written out per degree of freedom):
+ *   row_ptr host int64 [4*npoin+1]: row_ptr[4i+c] = 16*bptr[i] + 4*c*deg(i) (deg(i) = bptr[i+1]-bptr[i]),
+ *                                   row_ptr[4*npoin] = 16*nnzb;
+ *   col     host int32 [16*nnzb]:   the entries of scalar row 4i+c in (block, c') order,
+ *                                   col[row_ptr[4i+c] + 4*(k - bptr[i]) + c'] = 4*bcol[k] + c'.
+ * The value of that entry is values[k][c][c'] of nsa_assemble. Either array may be NULL. Requires the
+ * host copy (NSA_ESTATE after nsa_mesh_release_host); NSA_EUNSUPPORTED if 16*nnzb or 4*npoin exceeds
+ * the int32 column range. */
+nsa_status nsa_pattern_scalar_csr(const nsa_mesh *m, int64_t *row_ptr, int32_t *col);
 /* Colour classes: colour_ptr host int32 [ncolours+1], colour_elems host int32 [nelem] (element ids
  * grouped by colour, ascending inside a colour). Either may be NULL. */
 nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems);

@@ -1317,6 +1317,32 @@ nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol,
     return ok();
 }
 
+nsa_status nsa_pattern_scalar_csr(const nsa_mesh *m, int64_t *row_ptr, int32_t *col) {
+    if (!m) return fail(NSA_EINVAL, "nsa_pattern_scalar_csr: null mesh");
+    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    if (4 * m->npoin > INT32_MAX) return fail(NSA_EUNSUPPORTED, "scalar columns exceed int32");
+    if (row_ptr) {
+        for (int64_t i = 0; i < m->npoin; i++) {
+            const int64_t deg = m->bptr[i + 1] - m->bptr[i];
+            for (int c = 0; c < 4; c++) row_ptr[4 * i + c] = 16 * m->bptr[i] + 4 * c * deg;
+        }
+        row_ptr[4 * m->npoin] = 16 * m->nnzb;
+    }
+    if (col) {
+        parallel_for(m->npoin, [&](int64_t b, int64_t e) {
+            for (int64_t i = b; i < e; i++) {
+                const int64_t k0 = m->bptr[i], deg = m->bptr[i + 1] - k0;
+                for (int c = 0; c < 4; c++) {
+                    int32_t *out = col + 16 * k0 + 4 * c * deg;
+                    for (int64_t k = 0; k < deg; k++)
+                        for (int cp = 0; cp < 4; cp++) out[4 * k + cp] = 4 * m->bcol[k0 + k] + cp;
+                }
+            }
+        }, 1024);
+    }
+    return ok();
+}
+
 nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_colouring: null mesh");
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");

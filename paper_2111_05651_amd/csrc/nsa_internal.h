@@ -97,6 +97,10 @@ __host__ __device__ constexpr int64_t lds_nodes_off(int32_t nblk, int32_t nrows)
 __host__ __device__ constexpr int64_t lds_tile_doubles(int32_t nblk, int32_t nrows, int32_t nnodes) {
     return lds_nodes_off(nblk, nrows) + 6 * (int64_t)nnodes;
 }
+// LDS bytes of a tile workgroup.
+inline size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes) {
+    return (size_t)lds_tile_doubles(nblk, nrows, nnodes) * 8;
+}
 
 // Workgroup-to-tile order of the row-tiled kernels. Workgroup w runs on XCD w % 8; XCD x takes the
 // runs x, x + 8, x + 16, ... of kXcdRun consecutive tiles, in dispatch order. Neighbouring tiles of a
@@ -113,7 +117,6 @@ __host__ __device__ constexpr int64_t xcd_item(int64_t w) {
 }
 
 enum class TileKern { F64, Mixed };
-size_t tile_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnodes);
 hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s);
 // Batched form: desc[mesh] in device memory, work[t] = (mesh, local tile). grid_wgs 0: one workgroup
 // per item; otherwise a persistent grid of that many workgroups (a multiple of 8, fewer than the items).

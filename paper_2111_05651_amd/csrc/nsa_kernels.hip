@@ -866,10 +866,6 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
 
 }  // namespace
 
-size_t tile_lds_bytes(int32_t cap_blocks, int32_t cap_rows, int32_t cap_nodes) {
-    return (size_t)lds_tile_doubles(cap_blocks, cap_rows, cap_nodes) * 8;
-}
-
 // Raise a kernel's dynamic-LDS limit once (not at every launch, so launches can be captured).
 hipError_t ensure_lds(const void *kern, size_t bytes) {
     static std::mutex mu;

@@ -24,7 +24,7 @@ RESIDUAL_PLAN = 3
 # every symbol include/nsa.h declares
 EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_count", "nsa_pattern_fill",
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_set_tile_threads", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
-           "nsa_mesh_get_colouring", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
+           "nsa_mesh_get_colouring", "nsa_pattern_scalar_csr", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
            "nsa_assemble_batched", "nsa_fill_uniform", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_get_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.nsa_mesh_get_pattern.argtypes = [P, P, P, P]
     lib.nsa_mesh_get_colouring.argtypes = [P, P, P]
+    lib.nsa_pattern_scalar_csr.argtypes = [P, P, P]
     lib.nsa_mesh_get_tiles.argtypes = [P, i32, P, P, P, P, P, P]
     lib.nsa_mesh_get_gather.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.nsa_mesh_upload.argtypes = [P, P, sz, P]
@@ -223,6 +224,14 @@ class Mesh:
         emap = np.zeros((i.nelem, 4, 4), dtype=np.int32)
         _check(load().nsa_mesh_get_pattern(self._h, _ptr(bptr), _ptr(bcol), _ptr(emap)), "nsa_mesh_get_pattern")
         return bptr, bcol, emap
+
+    def scalar_csr(self):
+        """Scalar CSR view of the block pattern: (row_ptr int64 [4 npoin + 1], col int32 [16 nnzb])."""
+        i = self.info
+        row_ptr = np.zeros(4 * i.npoin + 1, dtype=np.int64)
+        col = np.zeros(16 * i.nnzb, dtype=np.int32)
+        _check(load().nsa_pattern_scalar_csr(self._h, _ptr(row_ptr), _ptr(col)), "nsa_pattern_scalar_csr")
+        return row_ptr, col
 
     def colouring(self):
         i = self.info

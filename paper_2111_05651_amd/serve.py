@@ -118,6 +118,7 @@ class Request:
     mu: float
     dt: float
     vel: object = None            # device tensor [npoin][3] float64, or None to draw from vel_seed
+    vel_ready: object = None      # event recorded on the submitting thread's stream after vel was written
     vel_seed: int | None = None
     keep: bool = False            # keep the outputs (and their budget) until release()
     timeout: float | None = None  # seconds from launch to completion before it is reported
@@ -212,7 +213,9 @@ class Server:
     def submit(self, mesh_id: int, rho: float, mu: float, dt: float, *, vel=None, vel_seed: int | None = None,
                keep: bool = False, timeout: float | None = None, arrival: float | None = None) -> Request:
         """Queue a request; returns at once. `arrival` overrides the arrival stamp (an open-loop
-        load generator passes the scheduled time)."""
+        load generator passes the scheduled time). A caller-owned `vel` may still be in the making
+        on the calling thread's current stream: the launch that reads it waits for everything that
+        stream had queued at this call."""
         if not 0 <= mesh_id < self.ex.nmesh:
             raise ValueError(f"mesh id {mesh_id} out of range [0, {self.ex.nmesh})")
         if not (rho > 0 and mu >= 0 and dt > 0 and np.isfinite([rho, mu, dt]).all()):
@@ -223,6 +226,9 @@ class Server:
             self.ex.check_velocity(mesh_id, vel)
         r = Request(0, int(mesh_id), float(rho), float(mu), float(dt), vel=vel, vel_seed=vel_seed, keep=keep,
                     timeout=self.timeout if timeout is None else timeout)
+        if vel is not None:
+            # the caller may still be writing vel on its own stream: the launch waits for this point
+            r.vel_ready = self.ex.mark_ready(vel)
         r.nelem = self.ex.mesh_elems(mesh_id)
         r.ntiles = self.ex.mesh_tiles(mesh_id)
         r.nbytes = self.ex.request_bytes(mesh_id, vel is None)
@@ -562,6 +568,14 @@ class GpuExecutor:
             raise ValueError(f"velocity of mesh {i} must be a contiguous float64 [{m.npoin}][3] tensor on "
                              f"{self.device}")
 
+    def mark_ready(self, vel):
+        """An event on the calling thread's current stream of vel's device, after whatever it has
+        queued so far (the writes of vel among them)."""
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(vel.device))
+        return ev
+
     def velocity(self, i, seed, out=None):
         """The velocity a request with this seed uses: U[-1,1)^3 per node, drawn on the device by the
         library's seeded generator (nsa_fill_uniform) on the current stream."""
@@ -586,8 +600,14 @@ class GpuExecutor:
                     raise ServerError("request placement does not match its size")
                 vals = self._view(r.offset, 16 * nnzb, (nnzb, 4, 4))
                 rhs = self._view(o_rhs, 4 * npoin, (npoin, 4))
-                v = r.vel if r.vel is not None else self.velocity(r.mesh_id, r.vel_seed,
-                                                                  self._view(o_vel, 3 * npoin, (npoin, 3)))
+                if r.vel is not None:
+                    # order the read of the caller's velocity after the work that produced it, and keep
+                    # its memory from being reused before this stream is done with it
+                    s.wait_event(r.vel_ready)
+                    r.vel.record_stream(s)
+                    v = r.vel
+                else:
+                    v = self.velocity(r.mesh_id, r.vel_seed, self._view(o_vel, 3 * npoin, (npoin, 3)))
                 vels.append(v)
                 outs.append((vals, rhs))
                 r.values, r.rhs, r.velocity = vals, rhs, v

@@ -159,6 +159,39 @@ def test_served_caller_velocity_and_concurrent_clients(meshes):
         r.release()
 
 
+def test_served_velocity_written_on_another_stream(meshes):
+    """A client writes each velocity on its own stream behind slow work and submits at once, without
+    synchronising: the server's launch waits for that stream, so every result equals the plain
+    kernel's on the finished velocity (colour mode: bitwise)."""
+    ex = GpuExecutor(meshes[:3], scatter=nsa.COLOUR, precision=nsa.MIXED, slots=2)
+    srv = Server(ex, budget_bytes=ex.resident_bytes + (1 << 30), timeout=30.0)
+    rng = np.random.default_rng(57)
+    srcs = [torch.from_numpy(rng.uniform(-1, 1, size=(m.npoin, 3))).cuda() for m in meshes[:3]]
+    a = torch.randn(2048, 2048, device="cuda")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    reqs = []
+    with srv:
+        for j in range(6):
+            i = j % 3
+            with torch.cuda.stream(side):
+                vel = torch.full_like(srcs[i], float("nan"))
+                for _ in range(8):      # slow work ahead of the write on the same stream
+                    a = torch.tanh(a @ a) * 0.5
+                vel.copy_(srcs[i])
+                reqs.append((i, vel, srv.submit(i, 1.0, 1e-3, 1e-2, vel=vel, keep=True)))
+        for i, _, r in reqs:
+            assert r.wait(30.0) and r.status == DONE, r.error
+    torch.cuda.synchronize()
+    for i, vel, r in reqs:
+        h = nsa.Mesh.from_inputs(meshes[i], tile_blocks=0).upload()
+        pv, pr = nsa.assemble(h, srcs[i], 1.0, 1e-3, 1e-2, precision=nsa.MIXED, scatter=nsa.COLOUR,
+                              kernel=nsa.KERNEL_TILED)
+        torch.cuda.synchronize()
+        assert torch.equal(r.values, pv) and torch.equal(r.rhs, pr)
+        r.release()
+
+
 def splitmix_uniform(n, seed, lo, hi):
     """lo + (hi - lo) * u_i, u_i = top 53 bits of splitmix64 at counter seed + (i + 1) * gamma,
     written from the generator's published definition (independent of the library's kernel)."""

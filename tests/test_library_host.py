@@ -46,6 +46,40 @@ def test_pattern_bit_exact(lib, cfg):
     assert mesh.nnzb == inputs.cube_counts(m.n)[3]
 
 
+@pytest.mark.parametrize("cfg", ["perm4", "hub2"])
+def test_scalar_csr_view(lib, cfg):
+    """The scalar CSR view against a NumPy expansion of the oracle's block pattern (bitwise), and the
+    value map it documents: scalar entry (4i+c, 4 bcol[k] + c') holds values[k][c][c'], checked on a
+    dense expansion of an oracle assembly."""
+    m = {"perm4": lambda: inputs.make_mesh(4, jitter=True, permute=True, seed=7),
+         "hub2": lambda: inputs.hub_mesh(2, seed=2)}[cfg]()
+    ob, oc, oe = oracle.pattern(m.npoin, m.lnods)
+    mesh = nsa.Mesh.from_inputs(m)
+    row_ptr, col = mesh.scalar_csr()
+    want_ptr, want_col = [0], []
+    for i in range(m.npoin):
+        cols = oc[ob[i]:ob[i + 1]]
+        for c in range(4):
+            want_col += [4 * int(j) + cp for j in cols for cp in range(4)]
+            want_ptr.append(len(want_col))
+    assert np.array_equal(row_ptr, np.array(want_ptr, dtype=np.int64))
+    assert np.array_equal(col, np.array(want_col, dtype=np.int32))
+    values, rhs = oracle.assemble(m, (ob, oc, oe))
+    dense = np.zeros((4 * m.npoin, 4 * m.npoin))
+    for i in range(m.npoin):
+        for k in range(ob[i], ob[i + 1]):
+            dense[4 * i:4 * i + 4, 4 * oc[k]:4 * oc[k] + 4] = values[k]
+    csr_vals = np.zeros(col.size)
+    for i in range(m.npoin):
+        k0, deg = ob[i], ob[i + 1] - ob[i]
+        for c in range(4):
+            base = row_ptr[4 * i + c]
+            for k in range(deg):
+                csr_vals[base + 4 * k: base + 4 * k + 4] = values[k0 + k][c]
+    rows = np.repeat(np.arange(4 * m.npoin), np.diff(row_ptr))
+    assert np.array_equal(dense[rows, col], csr_vals)
+
+
 def test_pattern_64_bit_exact(lib):
     m = inputs.make_mesh(24, jitter=True, permute=True, seed=9)
     ob, oc, oe = oracle.pattern(m.npoin, m.lnods)

@@ -52,6 +52,9 @@ class FakeExecutor:
         if len(vel) != self.sizes[i]:
             raise ValueError("wrong velocity length")
 
+    def mark_ready(self, vel):
+        return None
+
     def launch(self, slot, reqs):
         assert slot not in self.busy, "slot reused while busy"
         meshes = [r.mesh_id for r in reqs]
