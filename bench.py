@@ -13,6 +13,7 @@ import argparse
 import gc
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -70,6 +71,58 @@ def time_steps(fn, steps, warmup, stream):
     return total / steps, per, wall
 
 
+def timing_series(fn, stream, est_ms, seconds=1.0, cap=20000):
+    """Per-launch device times over a series of at least `seconds` of launches (after the contract's
+    K timed steps): count, total seconds, median, min and mean launch in ms."""
+    import math
+    import torch
+    n = max(20, min(cap, int(math.ceil(seconds * 1e3 / max(est_ms, 1e-3)))))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in evs]
+    return {"launches": n, "total_s": sum(per) / 1e3, "median_ms": statistics.median(per), "min_ms": min(per),
+            "mean_ms": statistics.fmean(per)}
+
+
+def bandwidth_probes(gib=2.0):
+    """What this device's HBM gives plain streams (the library's probe kernels, 16-byte accesses,
+    contiguous 256 KB chunks per workgroup): best of 10 launches of a read, a write and a copy of
+    `gib` GiB (copy: read + write bytes)."""
+    import torch
+    from paper_2111_05651_amd import nsa
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    sink = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    out = {"bytes": 8 * n}
+    for name, kind, src, dst, nbytes in (("read", nsa.PROBE_READ, a, sink, 8 * n),
+                                         ("write", nsa.PROBE_WRITE, None, b, 8 * n),
+                                         ("copy", nsa.PROBE_COPY, a, b, 16 * n)):
+        st = timing_series(lambda: nsa.bandwidth_probe(kind, src, dst), torch.cuda.current_stream(), 1.0,
+                           seconds=0.0, cap=10)
+        out[f"{name}_GBs"] = nbytes / (st["min_ms"] / 1e3) / 1e9
+    del a, b, sink
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_description():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def class_diff(a_values, a_rhs, b_values, b_rhs):
     """Per block class {uu, up, pu, pp} and RHS class {u, p}: max|a - b| / max|b|."""
     out = {}
@@ -86,34 +139,56 @@ def class_diff(a_values, a_rhs, b_values, b_rhs):
 
 
 def cpu_baseline(m, nelem_sample):
-    """The oracle (serial C, FP64) on the first nelem_sample elements of the same mesh."""
+    """The oracle on the first nelem_sample elements of the same mesh: its OpenMP build (the same C
+    source, element loop on all host threads, atomic adds) and, beside it, the serial build the tests
+    pin. FP64, pattern build untimed."""
     import oracle
     from paper_2111_05651_amd import inputs
     sub = inputs.Mesh(n=m.n, lnods=m.lnods[:nelem_sample].copy(), coord=m.coord, velocity=m.velocity,
                       rho=m.rho, mu=m.mu, dt=m.dt)
     pat = oracle.pattern(sub.npoin, sub.lnods)
+    omp = oracle.load_omp()
+    t0 = time.perf_counter()
+    oracle.assemble(sub, pat, lib=omp)
+    t_omp = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.assemble(sub, pat)
-    dt = time.perf_counter() - t0
-    return {"value": nelem_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nelem_sample} elements of the same mesh, serial FP64 C oracle "
-                      f"(pattern build untimed), {dt:.1f} s"}
+    t_ser = time.perf_counter() - t0
+    threads = int(omp.oracle_threads())
+    return {"value": nelem_sample / t_omp, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nelem_sample} elements of the same mesh, FP64 C oracle built with OpenMP on "
+                      f"{threads} threads ({t_omp:.1f} s); pattern build untimed",
+            "serial": {"value": nelem_sample / t_ser, "cores": 1, "seconds": t_ser}, **host_description()}
 
 
 def cpu_baseline_residual(m):
-    """The oracle's explicit-residual routine (serial C, FP64) on the whole mesh."""
+    """The oracle's explicit-residual routine on the whole mesh: its OpenMP build on all host threads
+    and, beside it, the serial build the tests pin. FP64."""
     import oracle
+    omp = oracle.load_omp()
+    t0 = time.perf_counter()
+    oracle.residual(m, lib=omp)
+    t_omp = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.residual(m)
-    dt = time.perf_counter() - t0
-    return {"value": m.nelem / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"all {m.nelem} elements of the same mesh, serial FP64 C oracle (residual outputs), "
-                      f"{dt:.1f} s"}
+    t_ser = time.perf_counter() - t0
+    threads = int(omp.oracle_threads())
+    return {"value": m.nelem / t_omp, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {m.nelem} elements of the same mesh, FP64 C oracle (residual outputs) built with "
+                      f"OpenMP on {threads} threads ({t_omp:.1f} s)",
+            "serial": {"value": m.nelem / t_ser, "cores": 1, "seconds": t_ser}, **host_description()}
 
 
 FLOPS_FILE = os.path.join(ROOT, "profiles", "residual_flops.json")
-PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector
-PEAK_FP32_TFLOPS = 78.6        # FP32 vector without packed instructions (the build disables them)
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector, published
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector, published (counts packed FP32 instructions)
+FP32_NO_PACKED_TFLOPS = 78.6   # 256 CUs x 64 FP32 lanes per clock x 2 (FMA) x 2.4 GHz: the library is
+                               # built without packed FP32 instructions
+# Floating-point operations per element of the method in the order of Listing 1, Gauss-point loops
+# included, as counted by the oracle's instrumented build (the same count on every mesh; a CPU test
+# checks both figures): the explicit-residual outputs, and the matrix and RHS.
+METHOD_FLOPS_RESIDUAL = 6913
+METHOD_FLOPS_ASSEMBLY = 6837
 
 
 def residual_flops(kernel_key):
@@ -150,32 +225,43 @@ def run_residual(args, m, prec):
 
     ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
+    series = timing_series(step, stream, ms, seconds=args.series_seconds)
+    log(f"timing series: {series['launches']} launches over {series['total_s']:.2f} s, median "
+        f"{series['median_ms']:.4f} ms, min {series['min_ms']:.4f} ms")
     beside = None
     if not args.no_beside:
         other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED
         first = [x.clone() for x in (r, t, w)]
         ms_o, _, _ = time_steps(lambda: step(other), args.steps, args.warmup, stream)
+        series_o = timing_series(lambda: step(other), stream, ms_o, seconds=args.series_seconds)
         f64, mix = (first, (r, t, w)) if other == nsa.MIXED else ((r, t, w), first)
         err = {n: float((a - b).abs().max() / b.abs().max()) for n, a, b in zip(("rhsid", "dt_rho", "mass_rho"), mix, f64)}
         beside = {"precision": "mixed" if other == nsa.MIXED else "fp64", "value": m.nelem / (ms_o / 1e3),
-                  "ms_per_step": ms_o, "unit": "elements/s", "same_gpu": True, "mixed_vs_fp64_error": err}
+                  "ms_per_step": ms_o, "unit": "elements/s", "same_gpu": True, "timing": series_o,
+                  "mixed_vs_fp64_error": err}
         log(f"{beside['precision']} beside it: {ms_o:.4f} ms/step; mixed vs FP64 errors {err}")
-    launch_ms = statistics.fmean(per)
+    launch_ms = series["mean_ms"]
     rt = "float" if prec == nsa.MIXED else "double"
     kname = f"k_residual<{rt},256>"
+    achieved = METHOD_FLOPS_RESIDUAL * m.nelem / (launch_ms / 1e3) / 1e12
+    peak = PEAK_FP64_TFLOPS if prec == nsa.FP64 else PEAK_FP32_TFLOPS
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": kname, "flops_per_element": METHOD_FLOPS_RESIDUAL,
+            "flops_basis": "the method's floating-point operations per element in the order of Listing 1 "
+                           "(Gauss-point loops included), counted once per element by the oracle's "
+                           "instrumented build; the kernel's closed forms for linear tetrahedra take fewer",
+            "avg_launch_ms": launch_ms,
+            "launch_ms_basis": f"mean of the {series['launches']} launches of the timing series"}
+    if prec == nsa.MIXED:
+        roof["peak_fp32_without_packed"] = FP32_NO_PACKED_TFLOPS
+        roof["frac_vs_fp32_without_packed"] = achieved / FP32_NO_PACKED_TFLOPS
     fl = residual_flops(f"{kname}@{args.workload}/rows{args.tile_rows_residual}")
     if fl:
-        flops = (fl["fp64_flops_per_element"] + fl["fp32_flops_per_element"]) * m.nelem
-        peak = PEAK_FP64_TFLOPS if prec == nsa.FP64 else PEAK_FP32_TFLOPS
-        achieved = flops / (launch_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": kname, "flops_per_element": flops / m.nelem,
-                "flops_basis": "VALU flops per element counted by rocprofv3 on this kernel",
-                "avg_launch_ms": launch_ms}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": kname, "avg_launch_ms": launch_ms,
-                "note": "no counter-measured flop count for this kernel source"}
+        valu = fl["fp64_flops_per_element"] + fl["fp32_flops_per_element"]
+        roof["valu_flops_per_element"] = valu
+        roof["valu_TFLOPs"] = valu * m.nelem / (launch_ms / 1e3) / 1e12
+        roof["valu_basis"] = ("VALU flops per element counted by rocprofv3 on this kernel source (every "
+                              "evaluation, re-evaluated elements included)")
     nbytes = 16 * m.nelem + 48 * m.npoin + 40 * m.npoin
     line = {
         "metric": "elements assembled/s (explicit-residual outputs)", "value": m.nelem / (ms / 1e3),
@@ -186,7 +272,7 @@ def run_residual(args, m, prec):
                    "precision": args.precision, "rows_per_tile": args.tile_rows_residual, "rho": m.rho, "mu": m.mu,
                    "dt": m.dt},
         "hbm_GBs": nbytes / (launch_ms / 1e3) / 1e9, "algorithmic_bytes_per_launch": nbytes,
-        "roofline": roof, "beside": beside,
+        "timing": series, "roofline": roof, "beside": beside,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle residual on the whole mesh ...")
@@ -269,6 +355,126 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_run(executor, sizes, mean_elems, rate_ref, frac, seed, seconds, args):
+    """One load level: Poisson arrivals at frac * rate_ref elements/s for `seconds` through a Server over
+    `executor`; p50/p99 latency (arrival to results ready), throughput and the scheduler's figures."""
+    import threading
+    import torch
+    from paper_2111_05651_amd import inputs
+    from paper_2111_05651_amd.serve import DONE, Server
+    lam = frac * rate_ref / mean_elems
+    nreq = max(1, int(math.ceil(lam * seconds)))
+    stream = inputs.served_requests(nreq, len(sizes), rate=lam, seed=seed)
+    srv = Server(executor, budget_bytes=int(args.serve_budget_gb * 2 ** 30), timeout=60.0,
+                 max_launch_elems=args.serve_launch_elems)
+    executor.intervals.clear()
+    reqs = []
+    gc.collect()
+    pauses, t_gc = [], [0.0]
+
+    def on_gc(phase, info):
+        if phase == "start":
+            t_gc[0] = time.perf_counter()
+        else:
+            pauses.append(time.perf_counter() - t_gc[0])
+    gc.callbacks.append(on_gc)
+    if args.serve_gc == "paused":
+        # the load generator's own policy: long-lived objects frozen, the cyclic collector off
+        # during the arrival window (reference counting still frees everything)
+        gc.freeze()
+        gc.disable()
+    mem0 = torch.cuda.memory_stats()
+    with srv:
+        start = time.perf_counter() + 0.05
+
+        def client():
+            for q in stream:
+                wait = start + q["t"] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                reqs.append(srv.submit(q["mesh"], q["rho"], q["mu"], q["dt"], vel_seed=q["vel_seed"],
+                                       arrival=start + q["t"]))
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        for r in reqs:
+            r.wait(120.0)
+    gc.enable()
+    gc.unfreeze()
+    gc.callbacks.remove(on_gc)
+    mem1 = torch.cuda.memory_stats()
+    st = srv.stats(t_start=start)
+    ov = executor.device_overlap()
+    done = [r for r in reqs if r.status == DONE]
+    wait = [r.t_launch - r.t_arrival for r in done]
+    service = [r.t_done - r.t_launch for r in done]
+
+    def pct(x, q):
+        return float(statistics.quantiles(x, n=100)[q - 1]) * 1e3 if len(x) > 1 else float("nan")
+    nbytes = sum(algorithmic_bytes(*sizes[r.mesh_id]) for r in done)
+    busy = ov.get("busy_ms", 0.0)
+    out = {"load": frac, "rate_per_s": lam, "requests": nreq, "done": len(done),
+           "p50_ms": st.get("p50", float("nan")) * 1e3, "p99_ms": st.get("p99", float("nan")) * 1e3,
+           "mean_ms": st.get("mean", float("nan")) * 1e3, "elements_per_s": st.get("elements_per_s"),
+           "offered_elements_per_s": lam * mean_elems, "launches": st["launches"],
+           "mean_launch_requests": st["mean_launch_requests"], "max_inflight": st["max_inflight"],
+           "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9, "rejected": st["rejected"],
+           "timeouts": st["timeout"], "device_busy_ms": busy,
+           "device_overlapping_launches": ov.get("overlapping", 0),
+           "hbm_GBs_while_busy": nbytes / (busy / 1e3) / 1e9 if busy > 0 else None,
+           "wait_ms_p50_p99": [pct(wait, 50), pct(wait, 99)],
+           "service_ms_p50_p99": [pct(service, 50), pct(service, 99)],
+           "gc_pauses": len(pauses), "gc_max_pause_ms": max(pauses, default=0.0) * 1e3,
+           "device_mallocs": mem1.get("num_device_alloc", 0) - mem0.get("num_device_alloc", 0),
+           "device_frees": mem1.get("num_device_free", 0) - mem0.get("num_device_free", 0)}
+    log(f"{'batched' if executor.mode == 'batched' else 'plain FP64'} at {frac:.0%}: "
+        f"{json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()})}")
+    return out
+
+
+
+def served_leg(args):
+    """Compact served leg of the default run: `--served-leg-meshes` resident jittered cubes (tets
+    log-uniform in [1e3, 5e6]), Poisson arrivals for `--served-leg-seconds` at `--served-leg-load` of
+    the batched form's throughput over those same meshes (one launch over all of them, measured
+    first), continuous batching in mixed precision; beside it plain FP64 launches served one at a
+    time on the same resident meshes and the same arrival stream."""
+    import torch
+    from paper_2111_05651_amd import inputs, nsa
+    from paper_2111_05651_amd.serve import GpuExecutor
+    t0 = time.perf_counter()
+    meshes = inputs.config_served(nmesh=args.served_leg_meshes)
+    ex = GpuExecutor(meshes, scatter=nsa.ATOMIC, precision=nsa.MIXED, slots=args.serve_slots, trace=True)
+    sizes = [(h.nelem, h.npoin, h.nnzb) for h in ex.meshes]
+    del meshes
+    log(f"served leg: {len(sizes)} resident meshes, {sum(x[0] for x in sizes)} tets, "
+        f"{ex.resident_bytes / 1e9:.2f} GB ({time.perf_counter() - t0:.1f} s)")
+    # reference rate: one batched mixed-precision launch over every resident mesh
+    b = nsa.Batch(ex.meshes, nsa.ATOMIC)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    vels = [torch.rand((h.npoin, 3), dtype=torch.float64, device="cuda:0", generator=g) - 0.5 for h in ex.meshes]
+    outs = b.alloc_outputs()
+    b.set_inputs(vels, [1.0] * len(vels), [1e-3] * len(vels), [1e-2] * len(vels), outs)
+    ms_b, _, _ = time_steps(lambda: b.assemble(nsa.MIXED), 10, 3, torch.cuda.current_stream())
+    rate = sum(x[0] for x in sizes) / (ms_b / 1e3)
+    log(f"served leg: batched launch over all meshes {ms_b:.3f} ms, {rate:.4g} elements/s")
+    del b, vels, outs
+    torch.cuda.empty_cache()
+    mean_elems = sum(x[0] for x in sizes) / len(sizes)
+    served = serve_run(ex, sizes, mean_elems, rate, args.served_leg_load, 60, args.served_leg_seconds, args)
+    plain = GpuExecutor(None, scatter=nsa.ATOMIC, precision=nsa.FP64, mode="plain", trace=True, resident=ex.meshes)
+    base = serve_run(plain, sizes, mean_elems, rate, args.served_leg_load, 60, args.served_leg_seconds, args)
+    out = {"workload": f"{len(sizes)} resident jittered cubes, tets log-uniform in [1e3, 5e6], "
+                       f"{sum(x[0] for x in sizes)} tets; Poisson arrivals for {args.served_leg_seconds:g} s at "
+                       f"{args.served_leg_load:.0%} of the batched throughput over the same meshes",
+           "reference_batched_ms": ms_b, "reference_batched_elements_per_s": rate,
+           "continuous_batching": served, "plain_fp64_one_at_a_time": base}
+    del ex, plain
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_serve(args):
     """Served load: 200 resident jittered cubes (tets log-uniform in [1e3, 5e6]), open-loop Poisson
     arrivals, one request = one assembly of a uniformly chosen mesh with a velocity drawn on the
@@ -316,79 +522,9 @@ def run_serve(args):
     del meshes
     mean_elems = sum(x[0] for x in sizes) / len(sizes)
 
-    def run(executor, frac, seed):
-        lam = frac * rate4 / mean_elems
-        nreq = max(1, int(math.ceil(lam * args.serve_seconds)))
-        stream = inputs.served_requests(nreq, len(sizes), rate=lam, seed=seed)
-        srv = Server(executor, budget_bytes=int(args.serve_budget_gb * 2 ** 30), timeout=60.0,
-                     max_launch_elems=args.serve_launch_elems)
-        executor.intervals.clear()
-        reqs = []
-        gc.collect()
-        pauses, t_gc = [], [0.0]
-
-        def on_gc(phase, info):
-            if phase == "start":
-                t_gc[0] = time.perf_counter()
-            else:
-                pauses.append(time.perf_counter() - t_gc[0])
-        gc.callbacks.append(on_gc)
-        if args.serve_gc == "paused":
-            # the load generator's own policy: long-lived objects frozen, the cyclic collector off
-            # during the arrival window (reference counting still frees everything)
-            gc.freeze()
-            gc.disable()
-        mem0 = torch.cuda.memory_stats()
-        with srv:
-            start = time.perf_counter() + 0.05
-
-            def client():
-                for q in stream:
-                    wait = start + q["t"] - time.perf_counter()
-                    if wait > 0:
-                        time.sleep(wait)
-                    reqs.append(srv.submit(q["mesh"], q["rho"], q["mu"], q["dt"], vel_seed=q["vel_seed"],
-                                           arrival=start + q["t"]))
-            th = threading.Thread(target=client)
-            th.start()
-            th.join()
-            for r in reqs:
-                r.wait(120.0)
-        gc.enable()
-        gc.unfreeze()
-        gc.callbacks.remove(on_gc)
-        mem1 = torch.cuda.memory_stats()
-        st = srv.stats(t_start=start)
-        ov = executor.device_overlap()
-        done = [r for r in reqs if r.status == DONE]
-        wait = [r.t_launch - r.t_arrival for r in done]
-        service = [r.t_done - r.t_launch for r in done]
-
-        def pct(x, q):
-            return float(statistics.quantiles(x, n=100)[q - 1]) * 1e3 if len(x) > 1 else float("nan")
-        nbytes = sum(algorithmic_bytes(*sizes[r.mesh_id]) for r in done)
-        busy = ov.get("busy_ms", 0.0)
-        out = {"load": frac, "rate_per_s": lam, "requests": nreq, "done": len(done),
-               "p50_ms": st.get("p50", float("nan")) * 1e3, "p99_ms": st.get("p99", float("nan")) * 1e3,
-               "mean_ms": st.get("mean", float("nan")) * 1e3, "elements_per_s": st.get("elements_per_s"),
-               "offered_elements_per_s": lam * mean_elems, "launches": st["launches"],
-               "mean_launch_requests": st["mean_launch_requests"], "max_inflight": st["max_inflight"],
-               "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9, "rejected": st["rejected"],
-               "timeouts": st["timeout"], "device_busy_ms": busy,
-               "device_overlapping_launches": ov.get("overlapping", 0),
-               "hbm_GBs_while_busy": nbytes / (busy / 1e3) / 1e9 if busy > 0 else None,
-               "wait_ms_p50_p99": [pct(wait, 50), pct(wait, 99)],
-               "service_ms_p50_p99": [pct(service, 50), pct(service, 99)],
-               "gc_pauses": len(pauses), "gc_max_pause_ms": max(pauses, default=0.0) * 1e3,
-               "device_mallocs": mem1.get("num_device_alloc", 0) - mem0.get("num_device_alloc", 0),
-               "device_frees": mem1.get("num_device_free", 0) - mem0.get("num_device_free", 0)}
-        log(f"{'batched' if executor.mode == 'batched' else 'plain FP64'} at {frac:.0%}: "
-            f"{json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()})}")
-        return out
-
     loads = [float(x) for x in args.serve_loads.split(",")]
-    served = [run(ex, f, 60 + k) for k, f in enumerate(loads)]
-    base = [run(plain, f, 60 + k) for k, f in enumerate(loads)]
+    served = [serve_run(ex, sizes, mean_elems, rate4, f, 60 + k, args.serve_seconds, args) for k, f in enumerate(loads)]
+    base = [serve_run(plain, sizes, mean_elems, rate4, f, 60 + k, args.serve_seconds, args) for k, f in enumerate(loads)]
     head = served[-1]
     hbm = head["hbm_GBs_while_busy"]
     line = {
@@ -436,6 +572,14 @@ def main():
     ap.add_argument("--no-beside", action="store_true",
                     help="skip timing the other precision beside (mixed beside FP64, or FP64 beside mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the HBM bandwidth probes")
+    ap.add_argument("--series-seconds", type=float, default=1.0,
+                    help="length of the per-launch timing series after the K timed steps")
+    ap.add_argument("--no-served-leg", dest="served_leg", action="store_false",
+                    help="skip the compact served leg of the default cube128 run")
+    ap.add_argument("--served-leg-meshes", type=int, default=40)
+    ap.add_argument("--served-leg-seconds", type=float, default=2.0)
+    ap.add_argument("--served-leg-load", type=float, default=0.8)
     ap.add_argument("--cpu-sample", type=int, default=0, help="elements for the CPU baseline (0 = the whole mesh)")
     ap.add_argument("--serve-meshes", type=int, default=200)
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="seconds of arrivals per load level")
@@ -478,6 +622,11 @@ def main():
     kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO,
             "gather": nsa.KERNEL_GATHER}[args.kernel]
 
+    probe = None
+    if not args.no_probe:
+        probe = bandwidth_probes()
+        log(f"bandwidth probes: read {probe['read_GBs']:.0f} GB/s, write {probe['write_GBs']:.0f} GB/s, "
+            f"copy {probe['copy_GBs']:.0f} GB/s (read + write)")
     t0 = time.perf_counter()
     m = make_workload(args.workload)
     log(f"workload {args.workload}: {m.nelem} tets, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
@@ -508,11 +657,15 @@ def main():
 
     ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
     log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
+    series = timing_series(step, stream, ms, seconds=args.series_seconds)
+    log(f"timing series: {series['launches']} launches over {series['total_s']:.2f} s, median "
+        f"{series['median_ms']:.4f} ms, min {series['min_ms']:.4f} ms")
     beside = None
     if not args.no_beside and kern != nsa.KERNEL_DIRECT:
         other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED
         first_v, first_r = values.clone(), rhs.clone()
         ms_o, _, _ = time_steps(lambda: step(other), args.steps, args.warmup, stream)
+        series_o = timing_series(lambda: step(other), stream, ms_o, seconds=args.series_seconds)
         # block-class error of the mixed result against the FP64 one (the FP64 kernel meets the
         # oracle to 1e-12 in the parity tests)
         if other == nsa.MIXED:
@@ -522,11 +675,12 @@ def main():
         del first_v, first_r
         beside = {"precision": "mixed" if other == nsa.MIXED else "fp64", "value": m.nelem / (ms_o / 1e3),
                   "ms_per_step": ms_o, "unit": "elements/s", "dtype": "f32+f64" if other == nsa.MIXED else "f64",
-                  "same_gpu": True, "mixed_vs_fp64_class_error": diff}
-        log(f"{beside['precision']} kernel beside it: {ms_o:.4f} ms/step; mixed vs FP64 class errors {diff}")
+                  "same_gpu": True, "timing": series_o, "mixed_vs_fp64_class_error": diff}
+        log(f"{beside['precision']} kernel beside it: {ms_o:.4f} ms/step (series median {series_o['median_ms']:.4f}); "
+            f"mixed vs FP64 class errors {diff}")
 
     nbytes = algorithmic_bytes(m.nelem, m.npoin, info.nnzb)
-    launch_ms = statistics.fmean(per)
+    launch_ms = series["mean_ms"]
     achieved = nbytes / (launch_ms / 1e3) / 1e9
     rt = "float" if prec == nsa.MIXED else "double"
     if gather:
@@ -539,6 +693,14 @@ def main():
         tb = args.tile_blocks if scat == nsa.ATOMIC else args.tile_blocks_colour
     key = f"{kname}@{args.workload}/tile{tb}"
     traffic = traffic_for(key, nbytes) if kern in (nsa.KERNEL_TILED, nsa.KERNEL_GATHER) else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": launch_ms,
+            "launch_ms_basis": f"mean of the {series['launches']} launches of the timing series"}
+    if probe:
+        roof.update({"probe_read_GBs": probe["read_GBs"], "probe_write_GBs": probe["write_GBs"],
+                     "probe_copy_GBs": probe["copy_GBs"], "frac_vs_probe_write": achieved / probe["write_GBs"],
+                     "frac_vs_probe_copy": achieved / probe["copy_GBs"]})
     line = {
         "metric": "elements assembled/s",
         "value": m.nelem / (ms / 1e3),
@@ -554,13 +716,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {m.name}", "nelem": m.nelem, "npoin": m.npoin,
                    "nnzb": info.nnzb, "precision": args.precision, "scatter": args.scatter,
-                   "kernel": args.kernel, "tile_blocks": tb, "rho": m.rho, "mu": m.mu, "dt": m.dt},
+                   "kernel": args.kernel, "tile_blocks": tb, "tile_threads": nthreads, "rho": m.rho, "mu": m.mu,
+                   "dt": m.dt},
         "hbm_GBs": achieved,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": kname,
-                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": launch_ms},
+        "timing": series,
+        "roofline": roof,
         "beside": beside,
     }
+    del values, rhs, vel, mesh
+    torch.cuda.empty_cache()
+    if args.served_leg and args.workload == "cube128":
+        line["served"] = served_leg(args)
+        head = line["served"]["continuous_batching"]
+        line["latency_ms"] = {"p50": head["p50_ms"], "p99": head["p99_ms"], "load": head["load"],
+                              "workload": line["served"]["workload"]}
     if not args.no_cpu_baseline:
         ns = min(args.cpu_sample, m.nelem) if args.cpu_sample > 0 else m.nelem
         log(f"cpu baseline: oracle on {ns} elements ...")

@@ -329,6 +329,19 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
                                  const nsa_options *opt, double *rhsid, double *dt_rho, double *mass_rho,
                                  void *stream);
 
+/* ---- measurement ----------------------------------------------------------------------------- */
+
+#define NSA_PROBE_READ 0
+#define NSA_PROBE_WRITE 1
+#define NSA_PROBE_COPY 2
+/* A plain HBM stream for calibrating the bandwidth the assembly achieves against what this device
+ * delivers (not part of the assembly): NSA_PROBE_READ reads src[0 .. n) (dst receives nothing unless
+ * the data hold a value no real input has: pass a device double), NSA_PROBE_WRITE writes dst[0 .. n),
+ * NSA_PROBE_COPY copies src into dst. n even, src/dst device FP64 arrays, 16-byte aligned, not
+ * overlapping. Each workgroup streams contiguous 256 KB chunks, two workgroups per CU. Asynchronous
+ * on stream. Errors: NSA_EINVAL, NSA_EHIP. */
+nsa_status nsa_bandwidth_probe(int32_t kind, const double *src, double *dst, int64_t n, void *stream);
+
 /* ---- synthetic inputs ---------------------------------------------------------------------- */
 
 /* Seeded uniform values (a convenience for synthetic inputs such as request velocities; not part

@@ -6,8 +6,8 @@ benchmark's CPU-baseline leg. The product path never imports it.
 The arithmetic lives in ``nsa_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``);
 this module only compiles it and marshals NumPy arrays through ctypes.
 """
-from .oracle import (build, load, element, element_integrals, validate, pattern, assemble,
+from .oracle import (build, load, load_omp, flops, element, element_integrals, validate, pattern, assemble,
                      assemble_rows, residual, OR_OK, OR_EINVAL, OR_ERANGE, OR_EDEGENERATE, OR_ENOMEM)
 
-__all__ = ["build", "load", "element", "element_integrals", "validate", "pattern", "assemble",
+__all__ = ["build", "load", "load_omp", "flops", "element", "element_integrals", "validate", "pattern", "assemble",
            "assemble_rows", "residual", "OR_OK", "OR_EINVAL", "OR_ERANGE", "OR_EDEGENERATE", "OR_ENOMEM"]

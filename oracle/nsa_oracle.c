@@ -23,10 +23,16 @@
  * each such reading is listed with the design notes of the repository.
  *
  * Compile: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so nsa_oracle.c -lm
- * (no FMA contraction, IEEE round-to-nearest; loops run in ascending index order).
+ * (no FMA contraction, IEEE round-to-nearest; loops run in ascending index order). That serial build
+ * is the oracle the tests pin and compare against. The same source built with -fopenmp runs the
+ * element loops of oracle_assemble and oracle_residual on all host threads with atomic adds into the
+ * global arrays (sums in a run-dependent order); it only times the CPU baseline.
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -376,24 +382,45 @@ int oracle_assemble(int64_t npoin, int64_t nelem, const int32_t *lnods, const do
 {
     memset(values, 0, sizeof(double) * 16 * (size_t)nnzb);
     memset(rhs, 0, sizeof(double) * 4 * (size_t)npoin);
+    int status = OR_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < nelem; e++) {
         element_t E;
         double X[PNODE][NDIME], U[PNODE][NDIME];
         calculate_transients(lnods + 4 * e, coord, veloc, X, U);
         int st = element_pipeline(X, U, rho, mu, dt, &E);
-        if (st != OR_OK) return st;
+        if (st != OR_OK) {
+#pragma omp atomic write
+            status = st;
+            continue;
+        }
         for (int a = 0; a < PNODE; a++) {
             for (int b = 0; b < PNODE; b++) {
                 double *blk = values + 16 * (size_t)emap[16 * e + 4 * a + b];
                 for (int c = 0; c < NDOFN; c++)
-                    for (int cp = 0; cp < NDOFN; cp++)
+                    for (int cp = 0; cp < NDOFN; cp++) {
+#pragma omp atomic
                         blk[4 * c + cp] += E.elauu[4 * a + c][4 * b + cp];
+                    }
             }
             double *r = rhs + 4 * (size_t)lnods[4 * e + a];
-            for (int c = 0; c < NDOFN; c++) r[c] += E.elrhs[4 * a + c];
+            for (int c = 0; c < NDOFN; c++) {
+#pragma omp atomic
+                r[c] += E.elrhs[4 * a + c];
+            }
         }
     }
-    return OR_OK;
+    return status;
+}
+
+/* Threads the element loops use: 1 in the serial build. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Explicit-residual assembly: the outputs of Listing 2 (rhsid, dt_rho_nsi, mass_rho_nsi) instead
@@ -413,27 +440,37 @@ int oracle_residual(int64_t npoin, int64_t nelem, const int32_t *lnods, const do
     memset(rhsid, 0, sizeof(double) * 3 * (size_t)npoin);
     memset(dt_rho, 0, sizeof(double) * (size_t)npoin);
     memset(mass_rho, 0, sizeof(double) * (size_t)npoin);
+    int status = OR_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < nelem; e++) {
         element_t E;
         double X[PNODE][NDIME], U[PNODE][NDIME];
         calculate_transients(lnods + 4 * e, coord, veloc, X, U);
         int st = element_pipeline(X, U, rho, mu, dt, &E);
-        if (st != OR_OK) return st;
+        if (st != OR_OK) {
+#pragma omp atomic write
+            status = st;
+            continue;
+        }
         for (int a = 0; a < PNODE; a++) {
             int64_t ipoin = lnods[4 * e + a];
             for (int c = 0; c < NDIME; c++) {
                 double r = E.elrhs[4 * a + c];
                 for (int b = 0; b < PNODE; b++)
                     for (int cp = 0; cp < NDIME; cp++) r -= E.elauu[4 * a + c][4 * b + cp] * E.elvel[b][cp];
+#pragma omp atomic
                 rhsid[3 * ipoin + c] += r;
             }
             double lump = 0.0;
             for (int g = 0; g < PGAUS; g++) lump += E.gpvol[g] * E.shape[g][a];
-            dt_rho[ipoin] += lump * E.tau1;
-            mass_rho[ipoin] += lump * rho;
+            const double dtr = lump * E.tau1, mr = lump * rho;
+#pragma omp atomic
+            dt_rho[ipoin] += dtr;
+#pragma omp atomic
+            mass_rho[ipoin] += mr;
         }
     }
-    return OR_OK;
+    return status;
 }
 
 /* Assembly restricted to a sample of rows, for checking large meshes one row at a time.

@@ -17,12 +17,77 @@ OR_OK, OR_EINVAL, OR_ERANGE, OR_EDEGENERATE, OR_ENOMEM = 0, -1, -2, -3, -4
 _lib = None
 
 
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
+
+
 def build(src: str = SRC, out: str = LIB) -> str:
-    """Compile the oracle with gcc (always rebuilds)."""
+    """Compile the oracle with gcc (always rebuilds): the serial build the tests pin, and the OpenMP
+    build of the same source that only times the CPU baseline."""
     tmp = out + ".tmp"
-    subprocess.run(["gcc", *CFLAGS, "-o", tmp, src, "-lm"], check=True)
+    subprocess.run(["gcc", *CFLAGS, "-Wno-unknown-pragmas", "-o", tmp, src, "-lm"], check=True)
     os.replace(tmp, out)
+    if out == LIB:
+        build_flops()
+        tmp = LIB_OMP + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-fopenmp", "-o", tmp, src, "-lm"], check=True)
+        os.replace(tmp, LIB_OMP)
     return out
+
+
+LIB_FLOPS = os.path.join(HERE, "liboracle_flops.so")
+FLOPS_SRC = os.path.join(HERE, "flops.cpp")
+
+
+def build_flops() -> str:
+    """The operation-counting build of the same source (flops.cpp)."""
+    tmp = LIB_FLOPS + ".tmp"
+    subprocess.run(["g++", "-O1", "-ffp-contract=off", "-std=c++17", "-fpermissive", "-w", "-fPIC", "-shared", "-o", tmp,
+                    FLOPS_SRC],
+                   check=True)
+    os.replace(tmp, LIB_FLOPS)
+    return LIB_FLOPS
+
+
+def flops(mesh, kind="residual", pat=None):
+    """Floating-point operations of the oracle's routine over the mesh (kind "residual": the
+    explicit-residual outputs; "assemble": matrix and RHS), counted by the instrumented build, and
+    the outputs it computed: (count, outputs)."""
+    if not os.path.exists(LIB_FLOPS):
+        build_flops()
+    lib = C.CDLL(LIB_FLOPS)
+    d, i64, P = C.c_double, C.c_int64, C.c_void_p
+    ln = np.ascontiguousarray(mesh.lnods, dtype=np.int32)
+    co, ve = _f64(mesh.coord), _f64(mesh.velocity)
+    st = C.c_int(0)
+    if kind == "residual":
+        f = lib.oracle_flops_residual
+        f.argtypes = [i64, i64, P, P, P, d, d, d, P, P, P, P]
+        f.restype = C.c_longlong
+        out = (np.zeros((mesh.npoin, 3)), np.zeros(mesh.npoin), np.zeros(mesh.npoin))
+        n = f(mesh.npoin, mesh.nelem, _p(ln), _p(co), _p(ve), mesh.rho, mesh.mu, mesh.dt, *[_p(o) for o in out],
+              C.byref(st))
+    else:
+        if pat is None:
+            pat = pattern(mesh.npoin, mesh.lnods)
+        bptr, _, emap = pat
+        f = lib.oracle_flops_assemble
+        f.argtypes = [i64, i64, P, P, P, d, d, d, i64, P, P, P, P]
+        f.restype = C.c_longlong
+        out = (np.zeros((int(bptr[-1]), 4, 4)), np.zeros((mesh.npoin, 4)))
+        em = np.ascontiguousarray(emap, dtype=np.int32)
+        n = f(mesh.npoin, mesh.nelem, _p(ln), _p(co), _p(ve), mesh.rho, mesh.mu, mesh.dt, int(bptr[-1]), _p(em),
+              *[_p(o) for o in out], C.byref(st))
+    if st.value != OR_OK:
+        raise ValueError(f"oracle flops status {st.value}")
+    return int(n), out
+
+
+def load_omp():
+    """The OpenMP build (all host threads; for timing the CPU baseline, never for parity)."""
+    if not os.path.exists(LIB_OMP):
+        build()
+    lib = _bind(C.CDLL(LIB_OMP))
+    return lib
 
 
 def _bind(lib):
@@ -42,6 +107,8 @@ def _bind(lib):
     lib.oracle_assemble_rows.restype = C.c_int
     lib.oracle_residual.argtypes = [i64, i64, P, P, P, d, d, d, P, P, P]
     lib.oracle_residual.restype = C.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = C.c_int
     return lib
 
 

@@ -15,20 +15,19 @@
 
 namespace {
 
-thread_local std::string g_last_error;
+// Message of the calling thread's last failed call (a fixed buffer: recording an error allocates nothing).
+thread_local char g_last_error[512];
 
 nsa_status fail(nsa_status st, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return st;
 }
 
 nsa_status ok() {
-    g_last_error.clear();
+    g_last_error[0] = '\0';
     return NSA_OK;
 }
 
@@ -1099,7 +1098,7 @@ const char *nsa_status_string(nsa_status st) {
     }
 }
 
-const char *nsa_last_error(void) { return g_last_error.c_str(); }
+const char *nsa_last_error(void) { return g_last_error; }
 
 int32_t nsa_version(void) { return 300; }
 
@@ -1796,6 +1795,42 @@ nsa_status batch_push_work(nsa_batch *b, hipStream_t s) {
     return NSA_OK;
 }
 
+// Check member i's inputs and outputs and fill its descriptor (the batched form and its
+// allocation-free variant).
+nsa_status member_desc(const nsa_mesh *m, int32_t scatter, int32_t i, const double *vel, double rho, double mu,
+                       double dt, double *values, double *rhs, int32_t accumulate, int32_t threads, nsa::TileArgs &t) {
+    const nsa::TilePlan &P = m->plan[scatter];
+    if (!(rho > 0.0) || !std::isfinite(rho) || !(mu >= 0.0) || !std::isfinite(mu) || !(dt > 0.0) || !std::isfinite(dt))
+        return fail(NSA_EINVAL, "mesh %d: need rho > 0, mu >= 0, dt > 0 (finite)", i);
+    if ((m->nelem > 0 && !vel) || (m->nnzb > 0 && !values) || (m->npoin > 0 && !rhs))
+        return fail(NSA_EINVAL, "mesh %d: null device array", i);
+    if (((uintptr_t)values | (uintptr_t)rhs) % 16) return fail(NSA_EINVAL, "mesh %d: misaligned output", i);
+    t = nsa::TileArgs{};
+    if (P.ok) {
+        t.ntiles = P.ntiles();
+        t.lds_bytes = P.lds;
+        t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
+        t.tile_rptr = (const int64_t *)(m->ws + P.r_rptr.off);
+        t.runs = (const uint4 *)(m->ws + P.r_runs.off);
+        t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
+        t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
+        t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
+        t.tile_npad = (const int32_t *)(m->ws + P.r_npad.off);
+        t.cap_nodes = P.cap_nodes;
+        t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
+        t.coord = (const double4 *)(m->ws + m->r_coord4.off);
+    }
+    t.vel = vel;
+    t.rho = rho;
+    t.mu = mu;
+    t.dt = dt;
+    t.accumulate = accumulate;
+    t.threads = threads;
+    t.values = values;
+    t.rhs = rhs;
+    return NSA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1889,38 +1924,9 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
     nsa_status st = hip_check(hipEventSynchronize(b->copied), "batch staging wait");
     if (st) return st;
     for (size_t i = 0; i < b->meshes.size(); i++) {
-        const nsa_mesh *m = b->meshes[i];
-        const nsa::TilePlan &P = m->plan[b->scatter];
-        if (!(rho[i] > 0.0) || !std::isfinite(rho[i]) || !(mu[i] >= 0.0) || !std::isfinite(mu[i]) ||
-            !(dt[i] > 0.0) || !std::isfinite(dt[i]))
-            return fail(NSA_EINVAL, "mesh %zu: need rho > 0, mu >= 0, dt > 0 (finite)", i);
-        if ((m->nelem > 0 && !vel[i]) || (m->nnzb > 0 && !values[i]) || (m->npoin > 0 && !rhs[i]))
-            return fail(NSA_EINVAL, "mesh %zu: null device array", i);
-        if (((uintptr_t)values[i] | (uintptr_t)rhs[i]) % 16) return fail(NSA_EINVAL, "mesh %zu: misaligned output", i);
-        nsa::TileArgs t;
-        if (P.ok) {
-            t.ntiles = P.ntiles();
-            t.lds_bytes = P.lds;
-            t.tile_row = (const int32_t *)(m->ws + P.r_row.off);
-            t.tile_rptr = (const int64_t *)(m->ws + P.r_rptr.off);
-            t.runs = (const uint4 *)(m->ws + P.r_runs.off);
-            t.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
-            t.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
-            t.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
-            t.tile_npad = (const int32_t *)(m->ws + P.r_npad.off);
-            t.cap_nodes = P.cap_nodes;
-            t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
-            t.coord = (const double4 *)(m->ws + m->r_coord4.off);
-        }
-        t.vel = vel[i];
-        t.rho = rho[i];
-        t.mu = mu[i];
-        t.dt = dt[i];
-        t.accumulate = accumulate;
-        t.threads = b->threads;
-        t.values = values[i];
-        t.rhs = rhs[i];
-        b->desc_host()[i] = t;
+        st = member_desc(b->meshes[i], b->scatter, (int32_t)i, vel[i], rho[i], mu[i], dt[i], values[i], rhs[i], accumulate,
+                         b->threads, b->desc_host()[i]);
+        if (st) return st;
     }
     hipStream_t s = (hipStream_t)stream;
     st = hip_check(hipMemcpyAsync(b->ws + b->r_desc.off, b->staging, b->meshes.size() * sizeof(nsa::TileArgs),
@@ -2017,6 +2023,20 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
     a.mass_rho = mass_rho;
     st = hip_check(nsa::launch_residual(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64, a,
                                         (hipStream_t)stream), "assemble (residual)");
+    return st ? st : ok();
+}
+
+nsa_status nsa_bandwidth_probe(int32_t kind, const double *src, double *dst, int64_t n, void *stream) {
+    if (kind < NSA_PROBE_READ || kind > NSA_PROBE_COPY || n < 0 || (n & 1) || !dst ||
+        (kind != NSA_PROBE_WRITE && !src))
+        return fail(NSA_EINVAL, "nsa_bandwidth_probe: bad arguments");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(NSA_EINVAL, "nsa_bandwidth_probe: 16-byte alignment");
+    if (kind == NSA_PROBE_COPY && src < dst + n && dst < src + n)
+        return fail(NSA_EINVAL, "nsa_bandwidth_probe: src and dst overlap");
+    int dev = 0, ncu = 256;
+    nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (!st) st = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "attribute");
+    if (!st) st = hip_check(nsa::launch_probe(kind, src, dst, n, 2 * ncu, (hipStream_t)stream), "probe");
     return st ? st : ok();
 }
 

@@ -19,6 +19,7 @@ FP64, MIXED = 0, 1
 ATOMIC, COLOUR = 0, 1
 KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT, KERNEL_GATHER = 0, 1, 2, 3
 GATHER_PLAN = 2
+PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
 RESIDUAL_PLAN = 3
 
 # every symbol include/nsa.h declares
@@ -26,7 +27,7 @@ EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_co
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_set_tile_threads", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_pattern_scalar_csr", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
-           "nsa_assemble_batched", "nsa_fill_uniform", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
+           "nsa_assemble_batched", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
 
 
 class NsaError(RuntimeError):
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_batch_set_inputs.argtypes = [P, P, P, P, P, P, P, i32, P]
     lib.nsa_assemble_batched.argtypes = [P, C.POINTER(Options), i32, P]
     lib.nsa_fill_uniform.argtypes = [P, i64, C.c_uint64, d, d, P]
+    lib.nsa_bandwidth_probe.argtypes = [i32, P, P, i64, P]
     lib.nsa_mesh_get_residual_tiles.argtypes = [P, P, P, P, P, P, P]
     lib.nsa_assemble_residual.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P, P]
     for name in EXPORTS:
@@ -377,6 +379,22 @@ def fill_uniform(out, seed: int, lo: float = -1.0, hi: float = 1.0, stream=None)
     _check(load().nsa_fill_uniform(out.data_ptr(), out.numel(), int(seed) % (1 << 64), float(lo), float(hi),
                                    _stream_handle(stream)), "nsa_fill_uniform")
     return out
+
+
+def bandwidth_probe(kind: int, src=None, dst=None, stream=None):
+    """One pass of a plain HBM stream (nsa_bandwidth_probe): PROBE_READ of src, PROBE_WRITE of dst or
+    PROBE_COPY src -> dst (contiguous float64 device tensors of the same, even size; for a read, dst
+    is a one-element device tensor)."""
+    import torch
+    for t in (src, dst):
+        if t is not None and not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous()
+                                  and t.is_cuda):
+            raise ValueError("probe buffers must be contiguous float64 device tensors")
+    n = (src if kind != PROBE_WRITE else dst).numel()
+    if kind == PROBE_COPY and dst.numel() < n:
+        raise ValueError("dst smaller than src")
+    _check(load().nsa_bandwidth_probe(int(kind), _ptr(src), _ptr(dst), n, _stream_handle(stream)),
+           "nsa_bandwidth_probe")
 
 
 class Batch:

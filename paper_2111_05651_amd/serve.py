@@ -47,11 +47,9 @@ ALIGN = 256
 
 
 def default_tile_blocks(scatter: int, precision: int, mode: str = "batched") -> int | None:
-    """Tile size of the resident meshes' plan: 336 blocks for batched mixed-precision atomic work (52.5
-    KB of LDS, so three 256-thread workgroups share a CU, which the mixed kernel's register count
-    allows), otherwise None (the library's default plan)."""
-    if mode == "batched" and scatter == nsa.ATOMIC and precision == nsa.MIXED:
-        return 336
+    """Tile size of the resident meshes' plan: None, the library's default plan, for every mode and
+    precision (both forms of the run-walking tile kernel hold two 256-thread workgroups per CU, so a
+    smaller tile would only leave lanes without runs)."""
     return None
 
 
