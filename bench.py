@@ -89,9 +89,9 @@ def timing_series(fn, stream, est_ms, seconds=1.0, cap=20000):
 
 
 def bandwidth_probes(gib=2.0):
-    """What this device's HBM gives plain streams (the library's probe kernels, 16-byte accesses,
-    contiguous 256 KB chunks per workgroup): best of 10 launches of a read, a write and a copy of
-    `gib` GiB (copy: read + write bytes)."""
+    """What this device's HBM gives plain streams (the library's probe kernels, 16-byte accesses, one
+    pass each): best of 10 launches of a read, a write and a copy of `gib` GiB (copy: read + write
+    bytes)."""
     import torch
     from paper_2111_05651_amd import nsa
     n = int(gib * 2 ** 30) // 8
@@ -223,11 +223,12 @@ def run_residual(args, m, prec):
     def step(p=prec):
         nsa.assemble_residual(mesh, vel, m.rho, m.mu, m.dt, precision=p, rhsid=r, dt_rho=t, mass_rho=w, stream=stream)
 
-    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
-    series = timing_series(step, stream, ms, seconds=args.series_seconds)
+    est, _, _ = time_steps(step, 3, 1, stream)
+    series = timing_series(step, stream, est, seconds=args.series_seconds)
     log(f"timing series: {series['launches']} launches over {series['total_s']:.2f} s, median "
         f"{series['median_ms']:.4f} ms, min {series['min_ms']:.4f} ms")
+    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
     beside = None
     if not args.no_beside:
         other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED
@@ -655,11 +656,14 @@ def main():
         nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=p, scatter=scat, kernel=kern, values=values,
                      rhs=rhs, stream=stream, block_threads=args.block_threads)
 
-    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
-    series = timing_series(step, stream, ms, seconds=args.series_seconds)
+    # the per-launch series (at least --series-seconds of launches) comes first, then the warmup and
+    # the K timed steps of the contract
+    est, _, _ = time_steps(step, 3, 1, stream)
+    series = timing_series(step, stream, est, seconds=args.series_seconds)
     log(f"timing series: {series['launches']} launches over {series['total_s']:.2f} s, median "
         f"{series['median_ms']:.4f} ms, min {series['min_ms']:.4f} ms")
+    ms, per, wall = time_steps(step, args.steps, args.warmup, stream)
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)")
     beside = None
     if not args.no_beside and kern != nsa.KERNEL_DIRECT:
         other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED

@@ -338,8 +338,9 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
  * delivers (not part of the assembly): NSA_PROBE_READ reads src[0 .. n) (dst receives nothing unless
  * the data hold a value no real input has: pass a device double), NSA_PROBE_WRITE writes dst[0 .. n),
  * NSA_PROBE_COPY copies src into dst. n even, src/dst device FP64 arrays, 16-byte aligned, not
- * overlapping. Each workgroup streams contiguous 256 KB chunks, two workgroups per CU. Asynchronous
- * on stream. Errors: NSA_EINVAL, NSA_EHIP. */
+ * overlapping. 16-byte accesses, one pass, each stream in the launch shape that measured fastest for
+ * it (reads grid-stride with several loads in flight per lane, writes and copies in contiguous 256 KB
+ * chunks per workgroup). Asynchronous on stream. Errors: NSA_EINVAL, NSA_EHIP. */
 nsa_status nsa_bandwidth_probe(int32_t kind, const double *src, double *dst, int64_t n, void *stream);
 
 /* ---- synthetic inputs ---------------------------------------------------------------------- */

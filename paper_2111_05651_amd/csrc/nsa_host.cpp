@@ -2036,7 +2036,7 @@ nsa_status nsa_bandwidth_probe(int32_t kind, const double *src, double *dst, int
     int dev = 0, ncu = 256;
     nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (!st) st = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "attribute");
-    if (!st) st = hip_check(nsa::launch_probe(kind, src, dst, n, 2 * ncu, (hipStream_t)stream), "probe");
+    if (!st) st = hip_check(nsa::launch_probe(kind, src, dst, n, ncu, (hipStream_t)stream), "probe");
     return st ? st : ok();
 }
 

@@ -126,8 +126,8 @@ hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work
 
 hipError_t ensure_lds(const void *kern, size_t bytes);
 
-// Bandwidth probes (kind 0 read, 1 write, 2 copy) over n doubles, `grid` workgroups.
-hipError_t launch_probe(int kind, const double *src, double *dst, int64_t n, int grid, hipStream_t s);
+// Bandwidth probes (kind 0 read, 1 write, 2 copy) over n doubles on a device of ncu compute units.
+hipError_t launch_probe(int kind, const double *src, double *dst, int64_t n, int ncu, hipStream_t s);
 
 // Gather tiles. Tile t owns the contiguous block rows [row[t], row[t+1]) as in the row tiles above,
 // with the same node table (owned rows first). Its elements are records rec[eptr[t] .. eptr[t+1])
