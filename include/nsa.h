@@ -306,6 +306,23 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
  * captured graph replays with whatever inputs the last nsa_batch_set_inputs installed. */
 nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int32_t grid_wgs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc): the batched form without a batch handle or workspace. The member
+ * descriptors, tile offsets and work table go into a fixed device array the library holds on each
+ * GPU it runs on (about 8.4 MB, kept until the process ends), written by two small kernels in stream
+ * order, then one launch of the tiled kernel over every tile of every mesh (one workgroup per
+ * tile). Arguments as nsa_batch_set_inputs (arrays of nmesh entries: device velocity [npoin][3],
+ * rho > 0, mu >= 0, dt > 0, device values [nnzb][4][4] and rhs [npoin][4], 16-byte aligned) plus the
+ * options of nsa_assemble_batched (opt->scatter picks the plan every mesh must have; accumulate as in
+ * nsa_options; NULL = FP64, atomic, overwrite). Limits: nmesh <= 256 and at most 2^20 tiles in total,
+ * else NSA_EINVAL with nothing launched. No hipMalloc, hipFree, memset, host copy or host
+ * synchronisation. Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, or other host threads) race and must be ordered by the caller; a call on one stream after
+ * another on the same stream is safe. */
+nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *meshes, const double *const *vel,
+                                       const double *rho, const double *mu, const double *dt, double *const *values,
+                                       double *const *rhs, const nsa_options *opt, void *stream);
+
 /* ---- explicit residual ---------------------------------------------------------------------- */
 
 /* Residual tiles (sizes from nsa_mesh_get_info; any array may be NULL): tile_row int32 [ntiles+1]

@@ -1972,6 +1972,71 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     return st ? st : ok();
 }
 
+nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *meshes, const double *const *vel,
+                                       const double *rho, const double *mu, const double *dt, double *const *values,
+                                       double *const *rhs, const nsa_options *opt, void *stream) {
+    if (nmesh <= 0 || !meshes || !vel || !rho || !mu || !dt || !values || !rhs)
+        return fail(NSA_EINVAL, "nsa_assemble_batched_static: null argument or nmesh <= 0");
+    if (nmesh > nsa::kStaticMeshes)
+        return fail(NSA_EINVAL, "nsa_assemble_batched_static: %d meshes, at most %d", nmesh, nsa::kStaticMeshes);
+    nsa_options o{};
+    if (opt) o = *opt;
+    if (o.precision != NSA_FP64 && o.precision != NSA_MIXED) return fail(NSA_EINVAL, "unknown precision %d", o.precision);
+    if (o.scatter != NSA_ATOMIC && o.scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", o.scatter);
+    if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
+    if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
+    for (int r : o.reserved)
+        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    int64_t total = 0;
+    int mdev = -1;
+    int32_t plan_threads = 0;
+    nsa_status st = check_members(nmesh, meshes, o.scatter, &total, &mdev, &plan_threads);
+    if (st) return st;
+    if (total > nsa::kStaticTiles)
+        return fail(NSA_EINVAL, "nsa_assemble_batched_static: %lld tiles, at most %lld", (long long)total,
+                    (long long)nsa::kStaticTiles);
+    int dev = -1;
+    st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != mdev) return fail(NSA_EINVAL, "meshes live on device %d, current is %d", mdev, dev);
+    if (!plan_threads) plan_threads = kPlanThreads[o.scatter];
+    const int threads = (o.scatter == NSA_ATOMIC && (o.block_threads == 128 || o.block_threads == 192 ||
+                                                       o.block_threads == 256))
+                            ? o.block_threads : plan_threads;
+    char *base = nullptr;
+    st = hip_check(nsa::static_scratch(&base), "static scratch address");
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // descriptors and first tiles, kDescChunk members per launch; then the work table; then the tiles
+    nsa::DescChunk c;
+    int64_t lds = 0, off = 0;
+    for (int32_t i0 = 0; i0 < nmesh; i0 += nsa::kDescChunk) {
+        c.first = i0;
+        c.count = std::min<int32_t>(nsa::kDescChunk, nmesh - i0);
+        for (int32_t j = 0; j < c.count; j++) {
+            const int32_t i = i0 + j;
+            st = member_desc(meshes[i], o.scatter, i, vel[i], rho[i], mu[i], dt[i], values[i], rhs[i], o.accumulate,
+                             plan_threads, c.d[j]);
+            if (st) return st;
+            c.toff[j] = off;
+            off += c.d[j].ntiles;
+            lds = std::max<int64_t>(lds, meshes[i]->plan[o.scatter].lds);
+        }
+        c.toff[c.count] = off;
+        st = hip_check(nsa::launch_put_desc(base, c, s), "descriptor launch");
+        if (st) return st;
+    }
+    if (off != total) return fail(NSA_EINVAL, "internal: tile count %lld != %lld", (long long)off, (long long)total);
+    st = hip_check(nsa::launch_fill_work(base, nmesh, total, s), "work table launch");
+    if (!st) st = hip_check(nsa::prepare_batch(threads, (size_t)kMaxTileLds), "batch LDS limit");
+    if (!st)
+        st = hip_check(nsa::launch_tiled_batch(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64,
+                                               (const nsa::TileArgs *)base,
+                                               (const int2 *)(base + nsa::kStaticWorkOff), total, threads, lds, 0, s),
+                       "assemble (batched, static tables)");
+    return st ? st : ok();
+}
+
 
 nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
                                  const nsa_options *opt, double *rhsid, double *dt_rho, double *mass_rho,

@@ -126,6 +126,27 @@ hipError_t launch_tiled_batch(TileKern k, const TileArgs *desc, const int2 *work
 
 hipError_t ensure_lds(const void *kern, size_t bytes);
 
+// Batched form without a workspace: the member descriptors, the tile offsets and the work table sit
+// in one file-scope device array per GPU (its address from static_scratch, taken once per device with
+// that device current). Layout: desc [kStaticMeshes] TileArgs, toff [kStaticMeshes + 1] int64 (first
+// tile of each member in the work list, toff[nmesh] = total), work [kStaticTiles] int2.
+constexpr int32_t kStaticMeshes = 256;
+constexpr int64_t kStaticTiles = int64_t(1) << 20;
+constexpr size_t kStaticToffOff = ((size_t)kStaticMeshes * sizeof(TileArgs) + 255) & ~size_t(255);
+constexpr size_t kStaticWorkOff = (kStaticToffOff + (size_t)(kStaticMeshes + 1) * 8 + 255) & ~size_t(255);
+constexpr size_t kStaticBytes = kStaticWorkOff + (size_t)kStaticTiles * 8;
+// Descriptors travel as kernel arguments, kDescChunk members per launch.
+constexpr int kDescChunk = 8;
+struct DescChunk {
+    TileArgs d[kDescChunk];
+    int64_t toff[kDescChunk + 1];  // first tile of each member, then the first tile after the chunk
+    int32_t first = 0;             // index of d[0] among the members
+    int32_t count = 0;             // members in this chunk (1 .. kDescChunk)
+};
+hipError_t static_scratch(char **ptr);
+hipError_t launch_put_desc(char *scratch, const DescChunk &c, hipStream_t s);
+hipError_t launch_fill_work(char *scratch, int32_t nmesh, int64_t total, hipStream_t s);
+
 // Bandwidth probes (kind 0 read, 1 write, 2 copy) over n doubles on a device of ncu compute units.
 hipError_t launch_probe(int kind, const double *src, double *dst, int64_t n, int ncu, hipStream_t s);
 

@@ -27,7 +27,7 @@ EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_co
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_set_tile_threads", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_pattern_scalar_csr", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
-           "nsa_assemble_batched", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
+           "nsa_assemble_batched", "nsa_assemble_batched_static", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
 
 
 class NsaError(RuntimeError):
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_batch_upload.argtypes = [P, P, sz, P]
     lib.nsa_batch_set_inputs.argtypes = [P, P, P, P, P, P, P, i32, P]
     lib.nsa_assemble_batched.argtypes = [P, C.POINTER(Options), i32, P]
+    lib.nsa_assemble_batched_static.argtypes = [i32, P, P, P, P, P, P, P, C.POINTER(Options), P]
     lib.nsa_fill_uniform.argtypes = [P, i64, C.c_uint64, d, d, P]
     lib.nsa_bandwidth_probe.argtypes = [i32, P, P, i64, P]
     lib.nsa_mesh_get_residual_tiles.argtypes = [P, P, P, P, P, P, P]
@@ -395,6 +396,33 @@ def bandwidth_probe(kind: int, src=None, dst=None, stream=None):
         raise ValueError("dst smaller than src")
     _check(load().nsa_bandwidth_probe(int(kind), _ptr(src), _ptr(dst), n, _stream_handle(stream)),
            "nsa_bandwidth_probe")
+
+
+def assemble_batched_static(meshes, vels, rho, mu, dt, outputs, precision=MIXED, scatter=ATOMIC, accumulate=False,
+                            block_threads=0, stream=None):
+    """The batched form without a batch handle or workspace (nsa_assemble_batched_static): one launch
+    over every tile of the uploaded meshes, the tables in the library's fixed per-GPU device array.
+    No device allocation. At most 256 meshes and 2^20 tiles; calls that overlap on one GPU race.
+    vels: device tensors [npoin][3]; rho, mu, dt: sequences; outputs: [(values, rhs), ...]."""
+    meshes, vels, outputs = list(meshes), list(vels), list(outputs)
+    n = len(meshes)
+    if not (len(vels) == len(outputs) == len(rho) == len(mu) == len(dt) == n):
+        raise ValueError(f"assemble_batched_static: expected {n} velocities, outputs and parameters each")
+    P = C.c_void_p
+    hs = (P * n)(*[m._h.value for m in meshes])
+    if any(m.ws is None for m in meshes):
+        raise ValueError("assemble_batched_static: every mesh must be uploaded (Mesh.upload)")
+    v = (P * n)(*[_dev_tensor(x, (m.npoin, 3), f"vels[{i}]", m.ws.device) for i, (x, m) in enumerate(zip(vels, meshes))])
+    va = (P * n)(*[_dev_tensor(o[0], (m.nnzb, 4, 4), f"outputs[{i}][0]", m.ws.device)
+                   for i, (o, m) in enumerate(zip(outputs, meshes))])
+    ra = (P * n)(*[_dev_tensor(o[1], (m.npoin, 4), f"outputs[{i}][1]", m.ws.device)
+                   for i, (o, m) in enumerate(zip(outputs, meshes))])
+    dr = (C.c_double * n)(*[float(x) for x in rho])
+    dm = (C.c_double * n)(*[float(x) for x in mu])
+    dd = (C.c_double * n)(*[float(x) for x in dt])
+    o = make_options(precision, scatter, accumulate=accumulate, block_threads=block_threads)
+    _check(load().nsa_assemble_batched_static(n, hs, v, dr, dm, dd, va, ra, C.byref(o), _stream_handle(stream)),
+           "nsa_assemble_batched_static")
 
 
 class Batch:

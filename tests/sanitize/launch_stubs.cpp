@@ -16,4 +16,7 @@ hipError_t ensure_lds(const void *, size_t) { return hipErrorNotSupported; }
 hipError_t launch_gather(TileKern, const GatherArgs &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_residual(TileKern, const ResArgs &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_probe(int, const double *, double *, int64_t, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t static_scratch(char **) { return hipErrorNotSupported; }
+hipError_t launch_put_desc(char *, const DescChunk &, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_fill_work(char *, int32_t, int64_t, hipStream_t) { return hipErrorNotSupported; }
 }  // namespace nsa
