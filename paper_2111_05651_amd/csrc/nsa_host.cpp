@@ -548,6 +548,23 @@ void run_order(const std::vector<nsa::RunRec> &runs, std::vector<int32_t> &order
     }
 }
 
+// Nodes that row r adds to the node list of tile `tid`: the row node itself (an owned row is in its
+// tile's node list even when no element touches it, so it has no diagonal block) and the columns of
+// its blocks not yet in the list.
+int64_t row_new_nodes(const nsa_mesh *m, const std::vector<int32_t> &stamp, int64_t r, int32_t tid) {
+    int64_t add = stamp[(size_t)r] != tid;
+    for (int64_t k = m->bptr[r]; k < m->bptr[r + 1]; k++) {
+        const int32_t c = m->bcol[k];
+        add += c != r && stamp[(size_t)c] != tid;
+    }
+    return add;
+}
+
+void stamp_row(const nsa_mesh *m, std::vector<int32_t> &stamp, int64_t r, int32_t tid) {
+    stamp[(size_t)r] = tid;
+    for (int64_t k = m->bptr[r]; k < m->bptr[r + 1]; k++) stamp[(size_t)m->bcol[k]] = tid;
+}
+
 // Row tiles for the tiled kernel (see nsa_internal.h). A tile is a contiguous row range whose LDS
 // footprint (block image, RHS rows, node table) stays within tile_blocks * 160 bytes and whose runs
 // number at most threads - 64 (threads for a one-wavefront workgroup): one run per lane, a single
@@ -607,13 +624,12 @@ nsa_status build_tiles(nsa_mesh *m, nsa::TilePlan &P, int32_t tile_blocks, int32
     for (int64_t r0 = 0; r0 < np; tid++) {
         int64_t r1 = r0, nodes = 0;
         while (r1 < np) {
-            int64_t add = 0;
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) add += stamp[m->bcol[k]] != tid;
+            const int64_t add = row_new_nodes(m, stamp, r1, tid);
             const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
             const int64_t need = (int64_t)nsa::tile_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
             const int64_t nruns = row_nruns[(size_t)r1 + 1] - row_nruns[(size_t)r0];
             if (r1 > r0 && (need > budget || r1 + 1 - r0 > kMaxTileRows || nruns > run_cap)) break;
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
+            stamp_row(m, stamp, r1, tid);
             nodes += add;
             r1++;
         }
@@ -737,8 +753,8 @@ nsa_status build_gather(nsa_mesh *m, nsa::GatherPlan &P, int32_t tile_blocks, in
     for (int64_t r0 = 0; r0 < np; tid++) {
         int64_t r1 = r0, nodes = 0, recs = 0, pairs = 0;
         while (r1 < np) {
-            int64_t addn = 0, adde = 0;
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) addn += stamp[m->bcol[k]] != tid;
+            const int64_t addn = row_new_nodes(m, stamp, r1, tid);
+            int64_t adde = 0;
             for (int64_t k = n2e_ptr[r1]; k < n2e_ptr[r1 + 1]; k++) adde += estamp[n2e[k]] != tid;
             const int64_t addp = 4 * (n2e_ptr[r1 + 1] - n2e_ptr[r1]);
             const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
@@ -750,7 +766,7 @@ nsa_status build_gather(nsa_mesh *m, nsa::GatherPlan &P, int32_t tile_blocks, in
                               pairs + addp > kMaxGatherPairs || nodes + addn > 65535;
             if (over && r1 > r0) break;
             if (over) return NSA_OK;  // one row alone does not fit: no gather plan for this mesh
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
+            stamp_row(m, stamp, r1, tid);
             for (int64_t k = n2e_ptr[r1]; k < n2e_ptr[r1 + 1]; k++) estamp[n2e[k]] = tid;
             nodes += addn;
             recs += adde;
@@ -896,11 +912,10 @@ nsa_status build_rtiles(nsa_mesh *m, nsa::ResPlan &P, int32_t tile_rows) {
     for (int64_t r0 = 0; r0 < np; tid++) {
         int64_t r1 = r0, nodes = 0;
         while (r1 < np) {
-            int64_t add = 0;
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) add += stamp[m->bcol[k]] != tid;
+            const int64_t add = row_new_nodes(m, stamp, r1, tid);
             const int64_t need = nsa::res_lds_bytes((int32_t)(nodes + add), (int32_t)(r1 + 1 - r0));
             if (r1 > r0 && (need > kResLds || r1 + 1 - r0 > tile_rows || nodes + add > 65535)) break;
-            for (int64_t k = m->bptr[r1]; k < m->bptr[r1 + 1]; k++) stamp[m->bcol[k]] = tid;
+            stamp_row(m, stamp, r1, tid);
             nodes += add;
             r1++;
         }

@@ -472,10 +472,15 @@ __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3],
 #pragma unroll
     for (int k = 0; k < 4; k++) dk0[k] = U[k][0] * g0[0] + U[k][1] * g0[1] + U[k][2] * g0[2];
     const R s0 = dk0[0] + dk0[1] + dk0[2] + dk0[3];
+    // w = sum_k d[k][0] U_k: then sum_k d[k][0] d[k][b] = w . grad N_b and sum_k d[k][b] = su . grad N_b,
+    // so no d[k][b] with b > 0 is formed
+    R w[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) w[c] = dk0[0] * U[0][c] + dk0[1] * U[1][c] + dk0[2] * U[2][c] + dk0[3] * U[3][c];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         const R un = su[c] + U[0][c];
-        const R au = s0 * su[c] + dk0[0] * U[0][c] + dk0[1] * U[1][c] + dk0[2] * U[2][c] + dk0[3] * U[3][c];
+        const R au = s0 * su[c] + w[c];
         rb[c] = rdt * v20 * (un + t1rho * au);
     }
     rb[3] = t1 * rdt * v4 * s0;
@@ -483,13 +488,11 @@ __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3],
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         const R *gb = C.gb[b];
-        R db[4];  // d[k][b]
-#pragma unroll
-        for (int k = 0; k < 4; k++) db[k] = U[k][0] * gb[0] + U[k][1] * gb[1] + U[k][2] * gb[2];
-        const R sb = db[0] + db[1] + db[2] + db[3];
-        const R gram = dk0[0] * db[0] + dk0[1] * db[1] + dk0[2] * db[2] + dk0[3] * db[3];
+        const R sb = su[0] * gb[0] + su[1] * gb[1] + su[2] * gb[2];        // sum_k d[k][b]
+        const R gram = w[0] * gb[0] + w[1] * gb[1] + w[2] * gb[2];         // sum_k d[k][0] d[k][b]
+        const R d0b = U[0][0] * gb[0] + U[0][1] * gb[1] + U[0][2] * gb[2];  // d[0][b]
         const R K = g0[0] * gb[0] + g0[1] * gb[1] + g0[2] * gb[2];
-        R T = tbase + ksb * sb + c1 * db[0] + c3 * dk0[b] + c2 * gram + muV * K;
+        R T = tbase + ksb * sb + c1 * d0b + c3 * dk0[b] + c2 * gram + muV * K;
         if (b == 0) T += Mo;
         C.T[b] = T;
         C.K[b] = K;

@@ -170,6 +170,43 @@ def test_isolated_nodes_match_oracle(lib):
     assert mb[11] == mb[10]
 
 
+def isolated_node_mesh(n=4, extra=12, seed=9):
+    """A jittered cube with `extra` nodes that belong to no element, spread through the numbering."""
+    m = inputs.make_mesh(n, jitter=True, seed=seed)
+    rng = np.random.default_rng(seed)
+    npoin = m.npoin + extra
+    spare = np.sort(rng.choice(npoin, size=extra, replace=False))
+    keep = np.setdiff1d(np.arange(npoin), spare)           # new id of old node i is keep[i]
+    coord = np.zeros((npoin, 3))
+    coord[keep] = m.coord
+    coord[spare] = rng.uniform(2.0, 3.0, size=(extra, 3))
+    vel = np.zeros((npoin, 3))
+    vel[keep] = m.velocity
+    return inputs.Mesh(n=m.n, lnods=keep[m.lnods].astype(np.int32), coord=coord, velocity=vel, rho=m.rho, mu=m.mu,
+                       dt=m.dt)
+
+
+def test_plans_cover_isolated_nodes(lib):
+    """An owned row without elements still sits in its tile's node list: every plan's LDS size must
+    count it (a node table past the allocation would overwrite what follows it)."""
+    m = isolated_node_mesh()
+    for tb, tbc, rows in ((512, 160, 256), (64, 64, 5)):
+        mesh = nsa.Mesh.from_inputs(m, tile_blocks=tb, tile_blocks_colour=tbc, tile_blocks_gather=tb,
+                                    tile_rows_residual=rows)
+        check_tile_plan(m, mesh, nsa.ATOMIC)
+        check_tile_plan(m, mesh, nsa.COLOUR)
+        check_gather_plan(m, mesh)
+        check_residual_plan(m, mesh)
+    empty = inputs.Mesh(n=0, lnods=np.zeros((0, 4), np.int32), coord=np.zeros((5, 3)), velocity=np.zeros((5, 3)),
+                        rho=1.0, mu=1e-3, dt=1e-2)
+    mesh = nsa.Mesh.from_inputs(empty)
+    info = mesh.info
+    t = mesh.tiles(nsa.ATOMIC)
+    nnod, nrows = np.diff(t["tile_nptr"]), np.diff(t["tile_row"])
+    assert np.array_equal(nnod, nrows)
+    assert info.tile_lds_bytes[nsa.ATOMIC] == max(((5 * r + 1) // 2 * 2 + 6 * r) * 8 for r in nrows)
+
+
 def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
     """Every index the tiled kernel derives from the plan stays inside its buffers, and the runs are
     what the kernel assumes: every (element, owned row) pair of a tile in exactly one run, element q
@@ -214,7 +251,8 @@ def check_tile_plan(m, mesh, scatter, lds_limit=160 * 1024):
         assert np.array_equal(nodes[:nr], np.arange(r0, r1))
         assert np.all(np.diff(nodes[nr:]) > 0) and not np.any((nodes[nr:] >= r0) & (nodes[nr:] < r1))
         els = sorted({e for i in range(r0, r1) for e in n2e[i]})
-        assert set(nodes.tolist()) == set(m.lnods[els].ravel().tolist())
+        # the owned rows (also those no element touches) and every node of the tile's elements
+        assert set(nodes.tolist()) == set(m.lnods[els].ravel().tolist()) | set(range(r0, r1))
         assert nodes.size <= 65535
         pairs = []
         for r, es in zip(runs, rel):
