@@ -448,7 +448,7 @@ struct Row0 {
 
 template <typename R>
 __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3], double rho_d, double mu_d,
-                                           double dt_d, Row0<R> &C, R rb[4]) {
+                                           double rdt_d, Row0<R> &C, R rb[4]) {
     R U[4][3];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -458,7 +458,7 @@ __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3],
             C.gb[a][c] = (R)g.G[a][c];
         }
     const R V = (R)g.V, h = (R)g.h, rh = (R)g.rh, rho = (R)rho_d, mu = (R)mu_d;
-    const R rdt = (R)(rho_d / dt_d);
+    const R rdt = (R)rdt_d;
     R su[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) su[c] = U[0][c] + U[1][c] + U[2][c] + U[3][c];
@@ -485,14 +485,18 @@ __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3],
     }
     rb[3] = t1 * rdt * v4 * s0;
     const R tbase = Mo + c3 * s0, ksb = c1 + c2 * s0;
+    // T_b = tbase + c3 d[b][0] + ksb s_b + c1 d[0][b] + c2 gram_0b + muV K_0b, and each of s_b, d[0][b],
+    // gram_0b, K_0b is a dot product with grad N_b: T_b = tbase + c3 d[b][0] + z . grad N_b with
+    // z = ksb su + c1 U_0 + c2 w + muV grad N_0
+    R z[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) z[c] = ksb * su[c] + c1 * U[0][c] + c2 * w[c] + muV * g0[c];
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         const R *gb = C.gb[b];
         const R sb = su[0] * gb[0] + su[1] * gb[1] + su[2] * gb[2];        // sum_k d[k][b]
-        const R gram = w[0] * gb[0] + w[1] * gb[1] + w[2] * gb[2];         // sum_k d[k][0] d[k][b]
-        const R d0b = U[0][0] * gb[0] + U[0][1] * gb[1] + U[0][2] * gb[2];  // d[0][b]
         const R K = g0[0] * gb[0] + g0[1] * gb[1] + g0[2] * gb[2];
-        R T = tbase + ksb * sb + c1 * d0b + c3 * dk0[b] + c2 * gram + muV * K;
+        R T = tbase + c3 * dk0[b] + (z[0] * gb[0] + z[1] * gb[1] + z[2] * gb[2]);
         if (b == 0) T += Mo;
         C.T[b] = T;
         C.K[b] = K;
@@ -563,10 +567,12 @@ __device__ __forceinline__ void block0(const Row0<R> &C, int b, double acc[16]) 
 // row (every element of the run adds to them), the block (row, hinge) (likewise) and the block
 // (row, k_new(q)), which element q+1 adds to again as its (row, k_old); that sum is complete after
 // element q+1 and goes into the LDS image then. Per element one block is added into LDS, per run
-// three blocks and the RHS row. Node data are read from the LDS node table for every element.
-template <typename R>
-__device__ __forceinline__ void tile_run(const TileArgs &A, const uint4 h, const uint4 k, double *acc, double *racc,
-                                         const double *nodes) {
+// three blocks and the RHS row.
+enum NodeLoads { NL_ALL, NL_REUSE, NL_AHEAD };
+
+template <typename R, int NL>
+__device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const uint4 h, const uint4 k, double *acc,
+                                         double *racc, const double *nodes) {
     const int row = (int)(h.x & 0xffffu), hinge = (int)(h.x >> 16);
     const int len = (int)(h.y >> 16);
     const int dslot = (int)(h.z & 0xffffu), jslot = (int)(h.z >> 16), last = (int)(h.w & 0xffffu);
@@ -575,22 +581,58 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, const uint4 h, const
     for (int i = 0; i < 16; i++) sd[i] = sj[i] = sa[i] = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; c++) sr[c] = 0.0;
+    // Node reads (NL): consecutive elements share the row, the hinge and one more node, so with
+    // NL_REUSE or NL_AHEAD each element reads one new node from the node table and keeps the others in
+    // registers; NL_AHEAD reads it one element ahead, before the current element's LDS adds (LDS
+    // operations complete in order, so a read issued after 16 adds waits for them). NL_ALL reads all
+    // four nodes per element (fewest registers).
+    constexpr bool kAhead = NL == NL_AHEAD;
+    double Xr[3], Ur[3], Xh[3], Uh[3], Xo[3], Uo[3], Xn[3], Un[3];
+    if (NL != NL_ALL) {
+        node_load(nodes, row, Xr, Ur);
+        node_load(nodes, hinge, Xh, Uh);
+        node_load(nodes, (int)(h.y & 0xffffu), Xo, Uo);
+    }
+    if (kAhead) node_load(nodes, (int)(k.x & 0xffffu), Xn, Un);
     int kold = (int)(h.y & 0xffffu);
     for (int q = 0; q < len; q++) {
         const int sh = (q & 1) * 16;
-        const int kn = (int)(((q < 2 ? k.x : k.y) >> sh) & 0xffffu);
         const int ks = (int)(((q < 2 ? k.z : k.w) >> sh) & 0xffffu);
+        const int kn = (int)(((q < 2 ? k.x : k.y) >> sh) & 0xffffu);
+        if (NL == NL_ALL) {
+            node_load(nodes, row, Xr, Ur);
+            node_load(nodes, hinge, Xh, Uh);
+            node_load(nodes, kold, Xo, Uo);
+        }
+        if (!kAhead) node_load(nodes, kn, Xn, Un);
+        kold = kn;
         Row0<R> C;
         R rb[4];
         {
             double X[4][3], U[4][3];
-            node_load(nodes, row, X[0], U[0]);
-            node_load(nodes, hinge, X[1], U[1]);
-            node_load(nodes, kold, X[2], U[2]);
-            node_load(nodes, kn, X[3], U[3]);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                X[0][c] = Xr[c];
+                X[1][c] = Xh[c];
+                X[2][c] = Xo[c];
+                X[3][c] = Xn[c];
+                U[0][c] = Ur[c];
+                U[1][c] = Uh[c];
+                U[2][c] = Uo[c];
+                U[3][c] = Un[c];
+            }
             Geo2 g;
             geometry2(X, g);
-            row0_setup<R>(g, U, A.rho, A.mu, A.dt, C, rb);
+            row0_setup<R>(g, U, A.rho, A.mu, rdt, C, rb);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            Xo[c] = Xn[c];
+            Uo[c] = Un[c];
+        }
+        if (kAhead && q + 1 < len) {
+            const int sh1 = ((q + 1) & 1) * 16;
+            node_load(nodes, (int)(((q + 1 < 2 ? k.x : k.y) >> sh1) & 0xffffu), Xn, Un);
         }
 #pragma unroll
         for (int c = 0; c < 4; c++) sr[c] += (double)rb[c];
@@ -599,7 +641,6 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, const uint4 h, const
         block0<R, false>(C, 2, sa);
         lds_add16(acc + kBlkStride * ks, sa);
         block0<R, true>(C, 3, sa);
-        kold = kn;
     }
     lds_add16(acc + kBlkStride * last, sa);
     lds_add16(acc + kBlkStride * jslot, sj);
@@ -611,7 +652,7 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, const uint4 h, const
 
 // One tile from prologue to write-out. Ends with a barrier so that the caller may start the next
 // tile's prologue on the same LDS.
-template <typename R, int NT>
+template <typename R, int NT, int NL>
 __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double *smem) {
     const int tid = threadIdx.x;
     // The node ids sit at a fixed stride per tile, so the first pass of node gathers needs no tile
@@ -662,8 +703,9 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     for (int i = tid; i < kRhsStride * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();
     // one run per lane (a tile with more runs than lanes takes several rounds)
+    const double rdt = A.rho / A.dt;
     while (p < p1) {
-        tile_run<R>(A, h, kk, acc, racc, nodes);
+        tile_run<R, NL>(A, rdt, h, kk, acc, racc, nodes);
         p += NT;
         if (p < p1) {
             h = A.runs[2 * p];
@@ -700,7 +742,11 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     // XCD-aware order (xcd_item): runs of consecutive tiles per XCD, drawn from the whole mesh
     const int64_t tile = xcd_item(blockIdx.x);
     if (tile >= A.ntiles) return;
-    run_tile<R, NT>(A, tile, smem);
+    // FP64: reusing node data costs 3 spilled registers and still wins, reading ahead spills more. The
+    // one-wavefront (deterministic) form reads as the batched FP64 kernel does, so that a mesh's
+    // deterministic result is the same bits alone and batched.
+    constexpr bool f64 = std::is_same<R, double>::value;
+    run_tile<R, NT, f64 ? (NT > 64 ? NL_REUSE : NL_ALL) : NL_AHEAD>(A, tile, smem);
 }
 
 // Batched form: one launch over the tiles of many meshes. work[t] = (mesh, tile of that mesh) with
@@ -729,6 +775,8 @@ template <typename R, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restrict__ desc, const int2 *__restrict__ work,
                                                       int64_t total) {
     extern __shared__ double smem[];
+    // the batched FP64 form keeps a member's arguments live as well: node data are re-read per element
+    constexpr int kBatchNL = std::is_same<R, double>::value ? NL_ALL : NL_AHEAD;
     if (PERSIST) {
         const int64_t per = (total + 7) / 8;
         const int64_t lo = (int64_t)(blockIdx.x & 7) * per;
@@ -738,14 +786,14 @@ __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restric
             const int2 w =
                 make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
             const TileArgs A = uniform_args(desc + w.x);
-            run_tile<R, NT>(A, w.y, smem);
+            run_tile<R, NT, kBatchNL>(A, w.y, smem);
         }
     } else {
         const int64_t t = xcd_item(blockIdx.x);
         if (t >= total) return;
         const int2 w = make_int2(__builtin_amdgcn_readfirstlane(work[t].x), __builtin_amdgcn_readfirstlane(work[t].y));
         const TileArgs A = uniform_args(desc + w.x);
-        run_tile<R, NT>(A, w.y, smem);
+        run_tile<R, NT, kBatchNL>(A, w.y, smem);
     }
 }
 
