@@ -677,9 +677,15 @@ def main():
         else:
             diff = class_diff(first_v, first_r, values, rhs)
         del first_v, first_r
+        # the library's own report (nsa_options.err_out): sampled element blocks, mixed against FP64
+        err = torch.zeros(12, dtype=torch.float64, device="cuda:0")
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=nsa.MIXED, scatter=scat, kernel=kern, values=values,
+                     rhs=rhs, stream=stream, err_out=err)
+        lib_err = nsa.error_report(err)
         beside = {"precision": "mixed" if other == nsa.MIXED else "fp64", "value": m.nelem / (ms_o / 1e3),
                   "ms_per_step": ms_o, "unit": "elements/s", "dtype": "f32+f64" if other == nsa.MIXED else "f64",
-                  "same_gpu": True, "timing": series_o, "mixed_vs_fp64_class_error": diff}
+                  "same_gpu": True, "timing": series_o, "mixed_vs_fp64_class_error": diff,
+                  "library_error_report": lib_err}
         log(f"{beside['precision']} kernel beside it: {ms_o:.4f} ms/step (series median {series_o['median_ms']:.4f}); "
             f"mixed vs FP64 class errors {diff}")
 

@@ -95,8 +95,29 @@ typedef struct nsa_options {
                                   the plan's, see nsa_mesh_set_tile_threads);
                                   ignored by the tiled colour mode (one wavefront per tile) */
     int32_t kernel;            /* NSA_KERNEL_AUTO, _TILED, _DIRECT or _GATHER */
-    int32_t reserved[3];       /* must be zero */
+    int32_t reserved;          /* must be zero */
+    double *err_out;           /* optional error report of nsa_assemble (NULL: none; the other
+                                  entry points take NULL only). Device pointer to 12 doubles,
+                                  8-byte aligned, written in stream order after the assembly:
+                                  NSA_ERR_SAMPLE elements spread evenly over the mesh (all of them
+                                  in a smaller mesh) are evaluated in the call's precision and in
+                                  FP64; per class k of NSA_ERR_UU .. NSA_ERR_RHS_P, err_out[k] =
+                                  max |value - FP64 value| and err_out[6 + k] = max |FP64 value|
+                                  over every element block entry (RHS entry) of the sample, so
+                                  err_out[k] / err_out[6 + k] is the class's relative error of the
+                                  mixed form (0 for NSA_FP64). Calls that overlap on one err_out
+                                  race. */
 } nsa_options;
+
+/* err_out classes: the velocity-velocity, velocity-pressure, pressure-velocity and
+ * pressure-pressure parts of the element blocks, then the velocity and pressure rows of the RHS */
+#define NSA_ERR_UU 0
+#define NSA_ERR_UP 1
+#define NSA_ERR_PU 2
+#define NSA_ERR_PP 3
+#define NSA_ERR_RHS_U 4
+#define NSA_ERR_RHS_P 5
+#define NSA_ERR_SAMPLE 4096       /* elements of a mesh sampled for err_out */
 
 typedef struct nsa_mesh_info {
     int64_t npoin, nelem, nnzb;

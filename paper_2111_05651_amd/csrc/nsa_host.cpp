@@ -1026,7 +1026,9 @@ void plan_layout(nsa_mesh *m) {
     take(m->r_ln_c, d ? 4 * ne * sizeof(int32_t) : 0);
     take(m->r_emap_c, d ? 16 * ne * sizeof(int32_t) : 0);
     const bool t = m->plan[0].ok || m->plan[1].ok || m->gplan.ok || m->rplan.ok;
-    take(m->r_coord4, t ? 4 * np * sizeof(double) : 0);
+    // coordinates as 32-byte records: the tiled kernels and the err_out sample read them
+    take(m->r_coord4, 4 * np * sizeof(double));
+    take(m->r_esamp, (size_t)std::min<int64_t>(m->nelem, NSA_ERR_SAMPLE) * 4 * sizeof(int32_t));
     take(m->r_bptr, t ? (np + 1) * sizeof(int64_t) : 0);
     for (nsa::TilePlan &P : m->plan) {
         take(P.r_row, P.ok ? P.row.size() * sizeof(int32_t) : 0);
@@ -1115,7 +1117,7 @@ const char *nsa_status_string(nsa_status st) {
 
 const char *nsa_last_error(void) { return g_last_error; }
 
-int32_t nsa_version(void) { return 300; }
+int32_t nsa_version(void) { return 310; }
 
 nsa_status nsa_pattern_count(int64_t npoin, int64_t nelem, const int32_t *lnods, int64_t *bptr,
                              int64_t *nnzb) {
@@ -1449,11 +1451,15 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         if (d)
             for (int64_t i = 0; i < np; i++)
                 for (int c = 0; c < 3; c++) co[c * np + i] = m->coord[3 * i + c];
-        std::vector<double> co4;
-        if (m->plan[0].ok || m->plan[1].ok || m->gplan.ok || m->rplan.ok) {
-            co4.assign(4 * (size_t)np, 0.0);
-            for (int64_t i = 0; i < np; i++)
-                for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
+        std::vector<double> co4(4 * (size_t)np, 0.0);
+        for (int64_t i = 0; i < np; i++)
+            for (int d = 0; d < 3; d++) co4[4 * i + d] = m->coord[3 * i + d];
+        // err_out sample: element floor(i nelem / ns) for i < ns, its four node ids
+        const int64_t ns = std::min<int64_t>(ne, NSA_ERR_SAMPLE);
+        std::vector<int32_t> esamp(4 * (size_t)ns);
+        for (int64_t i = 0; i < ns; i++) {
+            const int64_t e = i * ne / ns;
+            for (int a = 0; a < 4; a++) esamp[4 * i + a] = m->lnods[4 * e + a];
         }
         // per plan: block offset of each tile and its node ids at a fixed stride (padding repeats
         // the tile's first node, so every padded gather stays inside the mesh)
@@ -1479,7 +1485,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         const nsa::ResPlan &RP = m->rplan;
         const Up ups[] = {{m->r_ln, ln.data()}, {m->r_coord, co.data()}, {m->r_emap, em.data()},
                           {m->r_ln_c, lnc.data()}, {m->r_emap_c, emc.data()},
-                          {m->r_coord4, co4.data()}, {m->r_bptr, m->bptr.data()},
+                          {m->r_coord4, co4.data()}, {m->r_esamp, esamp.data()}, {m->r_bptr, m->bptr.data()},
                           {P0.r_row, P0.row.data()}, {P0.r_rptr, P0.rptr.data()}, {P0.r_nptr, P0.nptr.data()},
                           {P0.r_nodes, P0.nodes.data()}, {P0.r_runs, P0.runs.data()},
                           {P0.r_b0, b0v[0].data()}, {P0.r_npad, npad[0].data()},
@@ -1541,8 +1547,9 @@ nsa_status nsa_mesh_release_host(nsa_mesh *m) {
     return ok();
 }
 
-nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
-                        const nsa_options *opt, double *values, double *rhs, void *stream) {
+namespace {
+nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
+                         const nsa_options *opt, double *values, double *rhs, void *stream) {
     if (!m) return fail(NSA_EINVAL, "nsa_assemble: null mesh");
     if (!m->ws) return fail(NSA_ESTATE, "nsa_assemble: mesh not uploaded");
     nsa_options o{};
@@ -1552,11 +1559,11 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
     if (o.scatter != NSA_ATOMIC && o.scatter != NSA_COLOUR)
         return fail(NSA_EINVAL, "unknown scatter mode %d", o.scatter);
     if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
-    for (int r : o.reserved)
-        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
     if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED && o.kernel != NSA_KERNEL_DIRECT &&
         o.kernel != NSA_KERNEL_GATHER)
         return fail(NSA_EINVAL, "unknown kernel %d", o.kernel);
+    if ((uintptr_t)o.err_out % 8) return fail(NSA_EINVAL, "err_out must be 8-byte aligned");
     const nsa::TilePlan &P = m->plan[o.scatter];
     const nsa::GatherPlan &G = m->gplan;
     if (o.kernel == NSA_KERNEL_TILED && !P.ok)
@@ -1678,6 +1685,28 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
         }
     }
     return ok();
+}
+
+// The err_out report: the sampled elements in the call's precision and in FP64 (see nsa_options).
+nsa_status error_report(const nsa_mesh *m, const double *vel, double rho, double mu, double dt, bool mixed,
+                        double *err, hipStream_t s) {
+    nsa_status st = hip_check(nsa::launch_fill_zero(err, 12, s), "err_out clear");
+    if (st) return st;
+    const int64_t ns = std::min<int64_t>(m->nelem, NSA_ERR_SAMPLE);
+    if (ns == 0) return ok();
+    return hip_check(nsa::launch_err_sample((const int4 *)(m->ws + m->r_esamp.off), (int)ns,
+                                            (const double4 *)(m->ws + m->r_coord4.off), vel, rho, mu, rho / dt,
+                                            mixed, err, s),
+                     "err_out sample");
+}
+}  // namespace
+
+nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double mu, double dt,
+                        const nsa_options *opt, double *values, double *rhs, void *stream) {
+    nsa_status st = assemble_impl(m, vel, rho, mu, dt, opt, values, rhs, stream);
+    if (st || !opt || !opt->err_out) return st;
+    st = error_report(m, vel, rho, mu, dt, opt->precision == NSA_MIXED, opt->err_out, (hipStream_t)stream);
+    return st ? st : ok();
 }
 
 // ---- batched form ----------------------------------------------------------------------------
@@ -1966,8 +1995,8 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     if (o.precision != NSA_FP64 && o.precision != NSA_MIXED) return fail(NSA_EINVAL, "unknown precision %d", o.precision);
     if (o.scatter != b->scatter) return fail(NSA_EINVAL, "batch was built for scatter mode %d", b->scatter);
     if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
-    for (int r : o.reserved)
-        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     const int64_t total = b->ntiles;
     if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
     int dev = -1;
@@ -2000,8 +2029,8 @@ nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *mes
     if (o.scatter != NSA_ATOMIC && o.scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", o.scatter);
     if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
     if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
-    for (int r : o.reserved)
-        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     int64_t total = 0;
     int mdev = -1;
     int32_t plan_threads = 0;
@@ -2067,8 +2096,8 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
     if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED)
         return fail(NSA_EUNSUPPORTED, "the residual path has the tiled kernel only");
     if (o.block_threads != 0 && o.block_threads != 256) return fail(NSA_EINVAL, "block_threads must be 0 or 256");
-    for (int r : o.reserved)
-        if (r) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     const nsa::ResPlan &RP = m->rplan;
     if (!RP.ok && m->npoin > 0)
         return fail(NSA_EUNSUPPORTED, "no residual plan (nsa_mesh_set_tiling with NSA_RESIDUAL_PLAN before upload)");

@@ -40,6 +40,11 @@ enum class Kern { AtomicF64, AtomicMixed, ColourF64, ColourMixed };
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s);
 hipError_t launch_fill_uniform(double *p, int64_t n, uint64_t seed, double lo, double hi, hipStream_t s);
 hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s);
+// err_out report over ns sampled elements (node ids in samp): per class the largest |value - FP64
+// value| (0 unless mixed) and the largest |FP64 value| into err[0..5] and err[6..11], which must hold
+// zeros or earlier maxima (non-negative) on entry.
+hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, double rho, double mu,
+                             double rdt, bool mixed, double *err, hipStream_t s);
 
 // Row tiles: tile t owns the contiguous block rows [row[t], row[t+1]) and therefore the contiguous
 // blocks [bptr[r0], bptr[r1]). Its nodes tile_nodes[nptr[t] .. nptr[t+1]) are the owned rows (local
@@ -302,6 +307,7 @@ struct nsa_mesh {
     std::mutex plan_mu;
     // device layout (offsets into the caller's workspace)
     nsa::Region r_ln, r_coord, r_emap, r_ln_c, r_emap_c, r_coord4, r_bptr;
+    nsa::Region r_esamp;                // err_out sample: node ids of up to NSA_ERR_SAMPLE elements
     size_t ws_bytes = 0;
     char *ws = nullptr;                 // device, caller-owned
     int device = -1;

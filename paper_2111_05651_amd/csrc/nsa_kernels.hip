@@ -798,6 +798,96 @@ __global__ __launch_bounds__(NT, 2) void k_tiled_batch(const TileArgs *__restric
 }
 
 // ================================================================================================
+// err_out report of nsa_assemble: each sampled element evaluated with the tiled kernel's per-row code
+// (row0_setup, block0) in FP64 and, for the mixed form, in the mixed precision as well; every vertex in
+// turn is the local vertex 0 (the others in cyclic order; the geometry does not depend on the vertex
+// order). Per class the largest difference and the largest FP64 magnitude go into err[0..5] and
+// err[6..11] with atomic maxima on the bit patterns (non-negative doubles order as their bits).
+// ================================================================================================
+
+__device__ __forceinline__ void atomic_max_nonneg(double *p, double v) {
+    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ int err_class(int i) {  // entry i of a 4x4 block: uu, up, pu or pp
+    const int r = i >> 2, c = i & 3;
+    return r < 3 ? (c < 3 ? 0 : 1) : (c < 3 ? 2 : 3);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_err_sample(const int4 *__restrict__ samp, int ns,
+                                                    const double4 *__restrict__ coord, const double *__restrict__ vel,
+                                                    double rho, double mu, double rdt, double *err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double md[6], mr[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) md[k] = mr[k] = 0.0;
+    if (i < ns) {
+        const int4 e = samp[i];
+        const int n[4] = {e.x, e.y, e.z, e.w};
+        double X[4][3], U[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            const double4 c = coord[n[a]];
+            X[a][0] = c.x;
+            X[a][1] = c.y;
+            X[a][2] = c.z;
+#pragma unroll
+            for (int d = 0; d < 3; d++) U[a][d] = vel[3 * (int64_t)n[a] + d];
+        }
+        for (int a = 0; a < 4; a++) {
+            double Xa[4][3], Ua[4][3];
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    Xa[k][d] = X[(a + k) & 3][d];
+                    Ua[k][d] = U[(a + k) & 3][d];
+                }
+            Geo2 g;
+            geometry2(Xa, g);
+            Row0<double> C;
+            double rb[4];
+            row0_setup<double>(g, Ua, rho, mu, rdt, C, rb);
+            Row0<float> Cf;
+            float rbf[4];
+            if (MIXED) row0_setup<float>(g, Ua, rho, mu, rdt, Cf, rbf);
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int k = c < 3 ? 4 : 5;
+                mr[k] = fmax(mr[k], fabs(rb[c]));
+                if (MIXED) md[k] = fmax(md[k], fabs((double)rbf[c] - rb[c]));
+            }
+            for (int b = 0; b < 4; b++) {
+                double v[16], vf[16];
+                block0<double, true>(C, b, v);
+                if (MIXED) block0<float, true>(Cf, b, vf);
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const int k = err_class(j);
+                    mr[k] = fmax(mr[k], fabs(v[j]));
+                    if (MIXED) md[k] = fmax(md[k], fabs(vf[j] - v[j]));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            md[k] = fmax(md[k], __shfl_xor(md[k], o));
+            mr[k] = fmax(mr[k], __shfl_xor(mr[k], o));
+        }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            atomic_max_nonneg(err + k, md[k]);
+            atomic_max_nonneg(err + 6 + k, mr[k]);
+        }
+    }
+}
+
+// ================================================================================================
 // Explicit residual (the outputs of Listing 2 instead of a matrix): per owned row of an element,
 // the momentum residual RHS - sum_b A_uu(a, b) U_b (pressure zero), and the tau- and rho-weighted
 // lumped masses tau1 V/4 and rho V/4. The advection field and the previous-step velocity are the
@@ -945,6 +1035,17 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     if (nt == 128) return mixed ? go(k_tiled<float, 128>) : go(k_tiled<double, 128>);
     if (nt == 192) return mixed ? go(k_tiled<float, 192>) : go(k_tiled<double, 192>);
     return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
+}
+
+hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, double rho, double mu,
+                             double rdt, bool mixed, double *err, hipStream_t s) {
+    if (ns <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((ns + 255) / 256)), block(256);
+    if (mixed)
+        hipLaunchKernelGGL(k_err_sample<true>, grid, block, 0, s, samp, ns, coord, vel, rho, mu, rdt, err);
+    else
+        hipLaunchKernelGGL(k_err_sample<false>, grid, block, 0, s, samp, ns, coord, vel, rho, mu, rdt, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s) {

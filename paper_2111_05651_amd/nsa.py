@@ -38,7 +38,11 @@ class NsaError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("scatter", C.c_int32), ("accumulate", C.c_int32),
-                ("block_threads", C.c_int32), ("kernel", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("block_threads", C.c_int32), ("kernel", C.c_int32), ("reserved", C.c_int32),
+                ("err_out", C.c_void_p)]
+
+
+ERR_CLASSES = ("uu", "up", "pu", "pp", "rhs_u", "rhs_p")  # the classes of nsa_options.err_out
 
 
 class MeshInfo(C.Structure):
@@ -333,9 +337,11 @@ def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads
 
 
 def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP64, scatter=ATOMIC,
-             accumulate=False, block_threads=0, kernel=KERNEL_AUTO, values=None, rhs=None, stream=None):
+             accumulate=False, block_threads=0, kernel=KERNEL_AUTO, values=None, rhs=None, err_out=None,
+             stream=None):
     """Launch nsa_assemble on the stream (default: torch's current stream); returns (values, rhs)
-    as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given)."""
+    as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given). err_out: optional
+    float64 device tensor of 12 entries for the library's error report (see error_report)."""
     if mesh.ws is None:
         raise ValueError("the mesh has not been uploaded (Mesh.upload)")
     dev = mesh.ws.device
@@ -345,9 +351,18 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
     pval = _dev_tensor(values, (mesh.nnzb, 4, 4), "values", dev)
     prhs = _dev_tensor(rhs, (mesh.npoin, 4), "rhs", dev)
     o = make_options(precision, scatter, accumulate, block_threads, kernel)
+    if err_out is not None:
+        o.err_out = _dev_tensor(err_out, (12,), "err_out", dev)
     _check(load().nsa_assemble(mesh._h, pv, float(rho), float(mu), float(dt), C.byref(o), pval, prhs,
                                _stream_handle(stream)), "nsa_assemble")
     return values, rhs
+
+
+def error_report(err_out) -> dict:
+    """Relative error per class from an err_out tensor filled by assemble (synchronises): the largest
+    difference against FP64 over the sampled elements divided by the largest FP64 magnitude."""
+    e = err_out.cpu().tolist()
+    return {k: (e[i] / e[6 + i] if e[6 + i] > 0 else 0.0) for i, k in enumerate(ERR_CLASSES)}
 
 
 def assemble_residual(mesh: Mesh, vel, rho, mu, dt, precision=FP64, accumulate=False, rhsid=None, dt_rho=None,

@@ -479,3 +479,21 @@ def test_high_degree_hub(lib, level):
             check_tile_plan(m, mesh, scatter)
     assert info.residual_ntiles >= 1
     check_residual_plan(m, mesh)
+
+
+def test_options_layout_matches_header(tmp_path):
+    """The ctypes mirror of nsa_options has the C layout (size and the offset of every field), checked
+    against the header compiled by the host C compiler."""
+    import subprocess
+    fields = [f for f, _ in nsa.Options._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "nsa.h"\nint main(void) {\n'
+                   '  printf("%zu", sizeof(nsa_options));\n'
+                   + "".join(f'  printf(" %zu", offsetof(nsa_options, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    import ctypes
+    assert got[0] == ctypes.sizeof(nsa.Options) == 32
+    assert got[1:] == [getattr(nsa.Options, f).offset for f in fields]
