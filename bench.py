@@ -208,11 +208,12 @@ def run_residual(args, m, prec):
     """The explicit-residual outputs of Listing 2 (rhsid, dt_rho_nsi, mass_rho_nsi), no matrix."""
     import torch
     from paper_2111_05651_amd import nsa
+    cached = args.residual_geometry == "precomputed"
     mesh = nsa.Mesh.from_inputs(m, tile_blocks=0, tile_blocks_colour=0, tile_rows_residual=args.tile_rows_residual,
-                                keep_direct=False)
+                                keep_direct=False, residual_geometry=cached)
     mesh.upload("cuda:0")
     info = mesh.info
-    log(f"mesh registered: residual tiles={info.residual_ntiles} records/nelem="
+    log(f"mesh registered: residual tiles={info.residual_ntiles} geometry {args.residual_geometry} records/nelem="
         f"{info.residual_records / max(m.nelem, 1):.2f} lds={info.residual_lds_bytes}")
     vel = torch.from_numpy(m.velocity).to("cuda:0")
     r = torch.empty((m.npoin, 3), dtype=torch.float64, device="cuda:0")
@@ -243,7 +244,7 @@ def run_residual(args, m, prec):
         log(f"{beside['precision']} beside it: {ms_o:.4f} ms/step; mixed vs FP64 errors {err}")
     launch_ms = series["mean_ms"]
     rt = "float" if prec == nsa.MIXED else "double"
-    kname = f"k_residual<{rt},256>"
+    kname = f"k_residual<{rt},256>" if not cached else f"k_residual<{rt},256,precomputed geometry>"
     achieved = METHOD_FLOPS_RESIDUAL * m.nelem / (launch_ms / 1e3) / 1e12
     peak = PEAK_FP64_TFLOPS if prec == nsa.FP64 else PEAK_FP32_TFLOPS
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
@@ -271,7 +272,7 @@ def run_residual(args, m, prec):
         "dtype": "f32+f64" if prec == nsa.MIXED else "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {m.name}", "path": "residual", "nelem": m.nelem, "npoin": m.npoin,
                    "precision": args.precision, "rows_per_tile": args.tile_rows_residual, "rho": m.rho, "mu": m.mu,
-                   "dt": m.dt},
+                   "dt": m.dt, "geometry": args.residual_geometry},
         "hbm_GBs": nbytes / (launch_ms / 1e3) / 1e9, "algorithmic_bytes_per_launch": nbytes,
         "timing": series, "roofline": roof, "beside": beside,
     }
@@ -566,6 +567,9 @@ def main():
     ap.add_argument("--path", default="matrix", choices=["matrix", "residual"],
                     help="matrix: block-CSR values + RHS; residual: the explicit-residual outputs (no matrix)")
     ap.add_argument("--tile-rows-residual", type=int, default=256, help="rows per tile of the residual plan")
+    ap.add_argument("--residual-geometry", default="formed", choices=["formed", "precomputed"],
+                    help="residual path: element geometry formed from the coordinates in the kernel, or read "
+                         "from a per-element table stored at upload (nsa_mesh_set_residual_geometry)")
     ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
     ap.add_argument("--tile-threads", type=int, default=0, help="workgroup size of the atomic-mode plan (0 = default)")

@@ -352,6 +352,13 @@ nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *mes
  * [ntiles+1], tile_nodes int32 (owned rows first, then the other touched nodes ascending). */
 nsa_status nsa_mesh_get_residual_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems,
                                        uint16_t *local_nodes, int64_t *tile_nptr, int32_t *tile_nodes);
+/* Precomputed element geometry for the residual path (the paper's multi-engine design moves
+ * calculate_cartesian_derivatives off the engine, Sec. III-C): with cached = 1, nsa_mesh_upload also
+ * stores every element's FP64 geometry (gradients of the four shape functions, volume, element length
+ * and its inverse; 128 bytes per element) and, per residual record, the element id and its vertex
+ * order (8 bytes), and nsa_assemble_residual reads the geometry instead of forming it from the
+ * coordinates. Same results up to rounding. Default 0. Before nsa_mesh_upload (NSA_ESTATE after). */
+nsa_status nsa_mesh_set_residual_geometry(nsa_mesh *m, int32_t cached);
 /* The outputs of Listing 2's perform_assembly_in_global_system instead of a matrix: for every node
  * i (sums over the elements that contain it, a = the vertex of the element at i)
  *   rhsid[i][c]  += b_a[c] - sum_b sum_c' A_uu(a c, b c') U_b[c']    (c, c' = 0..2; the momentum

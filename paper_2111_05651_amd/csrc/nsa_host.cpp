@@ -1011,6 +1011,34 @@ nsa_status build_rtiles(nsa_mesh *m, nsa::ResPlan &P, int32_t tile_rows) {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// FP64 geometry of element e in its own vertex order: grad N_0..3 (J^-1 by cofactors, grad N_0 =
+// -(grad N_1 + grad N_2 + grad N_3)), V = |det J| / 6, h = |det J|^(1/3), 1/h, 0.
+void element_geometry(const nsa_mesh *m, int64_t e, double *g) {
+    double X[4][3];
+    for (int a = 0; a < 4; a++)
+        for (int d = 0; d < 3; d++) X[a][d] = m->coord[3 * (int64_t)m->lnods[4 * e + a] + d];
+    double J[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) J[r][c] = X[c + 1][r] - X[0][r];
+    const double cof[3][3] = {{J[1][1] * J[2][2] - J[1][2] * J[2][1], J[1][2] * J[2][0] - J[1][0] * J[2][2],
+                               J[1][0] * J[2][1] - J[1][1] * J[2][0]},
+                              {J[0][2] * J[2][1] - J[0][1] * J[2][2], J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                               J[0][1] * J[2][0] - J[0][0] * J[2][1]},
+                              {J[0][1] * J[1][2] - J[0][2] * J[1][1], J[0][2] * J[1][0] - J[0][0] * J[1][2],
+                               J[0][0] * J[1][1] - J[0][1] * J[1][0]}};
+    const double det = J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
+    // grad N_{s+1}[d] = (J^-1)[s][d] = cof[d][s] / det
+    for (int s = 0; s < 3; s++)
+        for (int d = 0; d < 3; d++) g[3 * (s + 1) + d] = cof[d][s] / det;
+    for (int d = 0; d < 3; d++) g[d] = -(g[3 + d] + g[6 + d] + g[9 + d]);
+    const double adet = std::fabs(det);
+    const double h = std::cbrt(adet);
+    g[12] = adet / 6.0;
+    g[13] = h;
+    g[14] = 1.0 / h;
+    g[15] = 0.0;
+}
+
 void plan_layout(nsa_mesh *m) {
     size_t off = 0;
     auto take = [&](nsa::Region &r, size_t bytes) {
@@ -1054,6 +1082,9 @@ void plan_layout(nsa_mesh *m) {
     take(RP.r_nptr, RP.ok ? RP.nptr.size() * sizeof(int64_t) : 0);
     take(RP.r_nodes, RP.ok ? RP.nodes.size() * sizeof(int32_t) : 0);
     take(RP.r_recs, RP.ok ? RP.recs.size() * sizeof(uint2) : 0);
+    const bool geo = RP.ok && m->res_geo_cached;
+    take(RP.r_geo, geo ? (size_t)m->nelem * nsa::kGeoDoubles * sizeof(double) : 0);
+    take(RP.r_rgel, geo ? RP.recs.size() * sizeof(uint2) : 0);
     m->ws_bytes = std::max<size_t>(off, 256);
 }
 
@@ -1281,6 +1312,17 @@ nsa_status nsa_mesh_keep_direct(nsa_mesh *m, int32_t keep) {
     return ok();
 }
 
+nsa_status nsa_mesh_set_residual_geometry(nsa_mesh *m, int32_t cached) {
+    if (!m || (cached != 0 && cached != 1)) return fail(NSA_EINVAL, "nsa_mesh_set_residual_geometry: bad arguments");
+    if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_residual_geometry after upload");
+    std::lock_guard<std::mutex> g(m->plan_mu);
+    if (m->res_geo_cached != (cached == 1)) {
+        m->res_geo_cached = cached == 1;
+        if (m->planned) plan_layout(m);
+    }
+    return ok();
+}
+
 nsa_status nsa_mesh_destroy(nsa_mesh *m) {
     delete m;
     return ok();
@@ -1477,6 +1519,35 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
                 for (int64_t i = 0; i < cap; i++) npad[k][t * cap + i] = P.nodes[a + (i < n ? i : 0)];
             }
         }
+        // precomputed residual geometry: per element (own vertex order) the FP64 gradients, volume,
+        // length and inverse length; per record the element and the element vertex of each local vertex
+        std::vector<double> geo;
+        std::vector<uint2> rgel;
+        const nsa::ResPlan &RG = m->rplan;
+        if (RG.ok && m->res_geo_cached) {
+            geo.assign((size_t)ne * nsa::kGeoDoubles, 0.0);
+            parallel_for(ne, [&](int64_t b, int64_t e) {
+                for (int64_t i = b; i < e; i++) element_geometry(m, i, &geo[(size_t)i * nsa::kGeoDoubles]);
+            });
+            rgel.resize(RG.recs.size());
+            const int64_t nt = RG.ntiles();
+            parallel_for(nt, [&](int64_t tb, int64_t te) {
+                for (int64_t t = tb; t < te; t++)
+                    for (int64_t p = RG.eptr[t]; p < RG.eptr[t + 1]; p++) {
+                        const int32_t el = RG.elems[p];
+                        const uint2 r = RG.recs[p];
+                        const uint32_t loc[4] = {r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16};
+                        uint32_t perm = 0;
+                        for (int a = 0; a < 4; a++) {
+                            const int32_t g = RG.nodes[RG.nptr[t] + loc[a]];
+                            int v = 0;
+                            while (v < 4 && m->lnods[4 * (int64_t)el + v] != g) v++;
+                            perm |= (uint32_t)(v & 3) << (2 * a);
+                        }
+                        rgel[p] = make_uint2((uint32_t)el, perm);
+                    }
+            });
+        }
         char *w = (char *)ws;
         nsa_status st;
         struct Up { const nsa::Region &r; const void *src; };
@@ -1496,7 +1567,8 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
                           {G.r_eptr, G.eptr.data()}, {G.r_recs, G.recs.data()}, {G.r_pptr, G.pptr.data()},
                           {G.r_pairs, G.pairs.data()}, {G.r_slots, G.slots.data()},
                           {RP.r_row, RP.row.data()}, {RP.r_eptr, RP.eptr.data()}, {RP.r_nptr, RP.nptr.data()},
-                          {RP.r_nodes, RP.nodes.data()}, {RP.r_recs, RP.recs.data()}};
+                          {RP.r_nodes, RP.nodes.data()}, {RP.r_recs, RP.recs.data()},
+                          {RP.r_geo, geo.data()}, {RP.r_rgel, rgel.data()}};
         for (const Up &u : ups) {
             if (!u.r.bytes) continue;
             st = hip_check(hipMemcpyAsync(w + u.r.off, u.src, u.r.bytes, hipMemcpyHostToDevice, s),
@@ -2130,6 +2202,10 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
     a.rhsid = rhsid;
     a.dt_rho = dt_rho;
     a.mass_rho = mass_rho;
+    if (RP.r_geo.bytes) {
+        a.geo = (const double *)(m->ws + RP.r_geo.off);
+        a.rgel = (const uint2 *)(m->ws + RP.r_rgel.off);
+    }
     st = hip_check(nsa::launch_residual(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64, a,
                                         (hipStream_t)stream), "assemble (residual)");
     return st ? st : ok();

@@ -240,7 +240,13 @@ struct ResArgs {
     double *rhsid = nullptr;             // [npoin][3]
     double *dt_rho = nullptr;            // [npoin]
     double *mass_rho = nullptr;          // [npoin]
+    // precomputed geometry (null: formed from the coordinates): geo[e] = grad N_0..3 (12), V, h, 1/h, 0
+    // for element e in its own vertex order; rgel[p] = (element of record p, vertex order: bits 2a..2a+1
+    // hold the element vertex at the record's local vertex a)
+    const double *geo = nullptr;
+    const uint2 *rgel = nullptr;
 };
+constexpr int kGeoDoubles = 16;
 constexpr int kResStride = 5;
 __host__ __device__ constexpr int64_t res_lds_bytes(int32_t nnod, int32_t nrows) {
     return 48 * (int64_t)nnod + 8 * (int64_t)kResStride * nrows;
@@ -256,6 +262,7 @@ struct ResPlan {
     std::vector<int32_t> nodes, elems;
     std::vector<uint2> recs;
     Region r_row, r_eptr, r_nptr, r_nodes, r_recs;
+    Region r_geo, r_rgel;         // precomputed geometry (nsa_mesh_set_residual_geometry)
     int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
 };
 
@@ -302,6 +309,7 @@ struct nsa_mesh {
     int32_t want_gather = 0;
     nsa::ResPlan rplan;                 // residual tiles (explicit-residual outputs)
     int32_t want_res = 0;
+    bool res_geo_cached = false;        // residual path reads precomputed element geometry
     bool planned = false;
     bool keep_direct = true;            // upload the direct kernel's SoA arrays
     std::mutex plan_mu;

@@ -902,9 +902,40 @@ __global__ __launch_bounds__(256) void k_err_sample(const int4 *__restrict__ sam
 // accumulators instead of 68.
 // ================================================================================================
 
-template <typename R>
-__device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, int nrows, const double *nodes,
-                                                 double *racc) {
+// Precomputed geometry (CACHED): an element's stored values v (its own vertex order) in the record's
+// vertex order, perm bits 2a..2a+1 = the element vertex at local vertex a.
+struct GeoRaw {
+    double v[kGeoDoubles];
+};
+
+__device__ __forceinline__ void geo_load(const ResArgs &A, uint32_t elem, GeoRaw &r) {
+    const double2 *src = reinterpret_cast<const double2 *>(A.geo + (int64_t)kGeoDoubles * elem);
+#pragma unroll
+    for (int i = 0; i < kGeoDoubles / 2; i++) {
+        const double2 q = src[i];
+        r.v[2 * i] = q.x;
+        r.v[2 * i + 1] = q.y;
+    }
+}
+
+__device__ __forceinline__ void cached_geometry(const GeoRaw &r, uint32_t perm, Geo2 &g) {
+    const double *v = r.v;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int e = (int)((perm >> (2 * a)) & 3u);
+        // select instead of indexing v with a run-time index (which would put v in scratch memory)
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+            g.G[a][d] = e == 0 ? v[d] : e == 1 ? v[3 + d] : e == 2 ? v[6 + d] : v[9 + d];
+    }
+    g.V = v[12];
+    g.h = v[13];
+    g.rh = v[14];
+}
+
+template <typename R, bool CACHED>
+__device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, const GeoRaw &gr, uint32_t perm, int nrows,
+                                                 const double *nodes, double *racc) {
     const int loc[4] = {(int)(w.x & 0xffffu), (int)(w.x >> 16), (int)(w.y & 0xffffu), (int)(w.y >> 16)};
     int nown = 0;
 #pragma unroll
@@ -922,7 +953,10 @@ __device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, int 
         U[a][2] = q2.y;
     }
     Geo2 g;
-    geometry2(X, g);
+    if (CACHED)
+        cached_geometry(gr, perm, g);
+    else
+        geometry2(X, g);
     ElemT<R> E;
     setup_t<R>(g, U, A.rho, A.mu, A.dt, E);
     const R mt = E.t1V * (R)0.25, mr = E.rho * E.v4;
@@ -952,7 +986,7 @@ __device__ __forceinline__ void residual_element(const ResArgs &A, uint2 w, int 
     }
 }
 
-template <typename R, int NT>
+template <typename R, int NT, bool CACHED>
 __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
     extern __shared__ double smem[];
     const int64_t tile = xcd_item(blockIdx.x);  // XCD-aware order as in k_tiled
@@ -967,6 +1001,17 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
     int64_t p = p0 + tid;
     uint2 cur = make_uint2(0u, 0u);
     if (p < p1) cur = A.rec[p];
+    // CACHED: the geometry of the next record is loaded while the current one is integrated, and the
+    // element id of the one after it an iteration earlier still, so no load waits on another in the loop
+    GeoRaw gc, gn;
+    uint2 ec = make_uint2(0u, 0u), en = ec;
+    if (CACHED) {
+        if (p < p1) {
+            ec = A.rgel[p];
+            geo_load(A, ec.x, gc);
+        }
+        if (p + NT < p1) en = A.rgel[p + NT];
+    }
     for (int i = tid; i < nnod; i += NT) {
         const int64_t gnode = A.tile_nodes[n0 + i];
         const double4 c = A.coord[gnode];
@@ -982,9 +1027,19 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
         const int64_t pn = p + NT;
         uint2 nxt = make_uint2(0u, 0u);
         if (pn < p1) nxt = A.rec[pn];
-        residual_element<R>(A, cur, nrows, nodes, racc);
+        uint2 en2 = make_uint2(0u, 0u);
+        if (CACHED) {
+            if (pn < p1) geo_load(A, en.x, gn);
+            if (pn + NT < p1) en2 = A.rgel[pn + NT];
+        }
+        residual_element<R, CACHED>(A, cur, gc, ec.y, nrows, nodes, racc);
         cur = nxt;
         p = pn;
+        if (CACHED) {
+            gc = gn;
+            ec = en;
+            en = en2;
+        }
     }
     __syncthreads();
     for (int i = tid; i < 3 * nrows; i += NT) {
@@ -1058,7 +1113,8 @@ hipError_t launch_residual(TileKern k, const ResArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(kern, grid, block, lds, s, a);
         return hipGetLastError();
     };
-    return k == TileKern::Mixed ? go(k_residual<float, 256>) : go(k_residual<double, 256>);
+    if (a.geo) return k == TileKern::Mixed ? go(k_residual<float, 256, true>) : go(k_residual<double, 256, true>);
+    return k == TileKern::Mixed ? go(k_residual<float, 256, false>) : go(k_residual<double, 256, false>);
 }
 
 hipError_t prepare_batch(int threads, size_t lds) {

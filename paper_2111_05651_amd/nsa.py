@@ -27,7 +27,8 @@ EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_co
            "nsa_mesh_create", "nsa_mesh_set_tiling", "nsa_mesh_set_tile_threads", "nsa_mesh_keep_direct", "nsa_mesh_destroy", "nsa_mesh_get_info", "nsa_mesh_get_pattern",
            "nsa_mesh_get_colouring", "nsa_pattern_scalar_csr", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
-           "nsa_assemble_batched", "nsa_assemble_batched_static", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual"]
+           "nsa_assemble_batched", "nsa_assemble_batched_static", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual",
+           "nsa_mesh_set_residual_geometry"]
 
 
 class NsaError(RuntimeError):
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.nsa_bandwidth_probe.argtypes = [i32, P, P, i64, P]
     lib.nsa_mesh_get_residual_tiles.argtypes = [P, P, P, P, P, P, P]
     lib.nsa_assemble_residual.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P, P]
+    lib.nsa_mesh_set_residual_geometry.argtypes = [P, i32]
     for name in EXPORTS:
         if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
             getattr(lib, name).restype = i32
@@ -168,7 +170,7 @@ class Mesh:
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
                  tile_blocks_colour: int | None = None, keep_direct: bool = True,
                  tile_blocks_gather: int | None = None, tile_rows_residual: int | None = None,
-                 tile_threads: int | None = None):
+                 tile_threads: int | None = None, residual_geometry: bool = False):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
@@ -190,14 +192,17 @@ class Mesh:
             _check(lib.nsa_mesh_set_tiling(h, RESIDUAL_PLAN, int(tile_rows_residual)), "nsa_mesh_set_tiling")
         if not keep_direct:
             _check(lib.nsa_mesh_keep_direct(h, 0), "nsa_mesh_keep_direct")
+        if residual_geometry:
+            _check(lib.nsa_mesh_set_residual_geometry(h, 1), "nsa_mesh_set_residual_geometry")
         self.info = self._info()
 
     @classmethod
     def from_inputs(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None,
                     tile_blocks_gather: int | None = None, keep_direct: bool = True,
-                    tile_rows_residual: int | None = None, tile_threads: int | None = None) -> "Mesh":
+                    tile_rows_residual: int | None = None, tile_threads: int | None = None,
+                    residual_geometry: bool = False) -> "Mesh":
         return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather,
-                   tile_rows_residual, tile_threads)
+                   tile_rows_residual, tile_threads, residual_geometry)
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")

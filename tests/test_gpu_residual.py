@@ -104,3 +104,33 @@ def test_full_meshes(name):
         err = errors(run(mesh, m, precision), ref)
         say(f"[residual] {name} precision={precision} errors {err}")
         assert max(err.values()) <= tol(precision), err
+
+
+@pytest.mark.parametrize("cfg", ["cube7_perm", "cube5_rcm", "cube1"])
+@pytest.mark.parametrize("rows", [1, 64, 256])
+@pytest.mark.parametrize("precision", [nsa.FP64, nsa.MIXED], ids=["fp64", "mixed"])
+def test_precomputed_geometry(cfg, rows, precision):
+    """nsa_mesh_set_residual_geometry: the residual kernel reading stored element geometry (in the
+    record's vertex order) gives the oracle's outputs, and within 1e-12 the formed-geometry kernel's."""
+    m = SMALL[cfg]()
+    say(f"[residual] cached geometry {cfg} rows={rows} precision={precision}")
+    ref = oracle.residual(m)
+    cached = nsa.Mesh.from_inputs(m, tile_blocks=0, tile_blocks_colour=0, tile_rows_residual=rows,
+                                  residual_geometry=True).upload()
+    plain = nsa.Mesh.from_inputs(m, tile_blocks=0, tile_blocks_colour=0, tile_rows_residual=rows).upload()
+    got = run(cached, m, precision)
+    err = errors(got, ref)
+    assert max(err.values()) <= tol(precision), (cfg, rows, err)
+    same = errors(got, run(plain, m, precision))
+    assert max(same.values()) <= (1e-12 if precision == nsa.FP64 else 1e-6), same
+
+
+def test_precomputed_geometry_cube64():
+    m = inputs.config_64()
+    ref = oracle.residual(m)
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks=0, tile_blocks_colour=0, tile_rows_residual=256, keep_direct=False,
+                                residual_geometry=True).upload()
+    for precision in (nsa.FP64, nsa.MIXED):
+        err = errors(run(mesh, m, precision), ref)
+        say(f"[residual] cached geometry cube64 precision={precision} errors {err}")
+        assert max(err.values()) <= tol(precision), err
