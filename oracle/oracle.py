@@ -9,6 +9,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "nsa_oracle.c")
+Q1_SRC = os.path.join(HERE, "nsa_oracle_q1.c")  # the 2-D quadrilateral family
 LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
 
@@ -20,16 +21,16 @@ _lib = None
 LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 
-def build(src: str = SRC, out: str = LIB) -> str:
+def build(src: str = SRC, out: str = LIB, q1_src: str = Q1_SRC) -> str:
     """Compile the oracle with gcc (always rebuilds): the serial build the tests pin, and the OpenMP
-    build of the same source that only times the CPU baseline."""
+    build of the same sources that only times the CPU baseline."""
     tmp = out + ".tmp"
-    subprocess.run(["gcc", *CFLAGS, "-Wno-unknown-pragmas", "-o", tmp, src, "-lm"], check=True)
+    subprocess.run(["gcc", *CFLAGS, "-Wno-unknown-pragmas", "-o", tmp, src, q1_src, "-lm"], check=True)
     os.replace(tmp, out)
     if out == LIB:
         build_flops()
         tmp = LIB_OMP + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, "-fopenmp", "-o", tmp, src, "-lm"], check=True)
+        subprocess.run(["gcc", *CFLAGS, "-fopenmp", "-o", tmp, src, q1_src, "-lm"], check=True)
         os.replace(tmp, LIB_OMP)
     return out
 
@@ -109,6 +110,16 @@ def _bind(lib):
     lib.oracle_residual.restype = C.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = C.c_int
+    lib.oracle_q1_element_rule.argtypes = [P, P, d, d, d, C.c_int, P, P]
+    lib.oracle_q1_element_rule.restype = C.c_int
+    lib.oracle_q1_element.argtypes = [P, P, d, d, d, P, P]
+    lib.oracle_q1_element.restype = C.c_int
+    lib.oracle_q1_element_integrals.argtypes = [P, P, d, d, d, P, P, P, P, P]
+    lib.oracle_q1_element_integrals.restype = C.c_int
+    lib.oracle_q1_validate.argtypes = [i64, i64, P, P, P]
+    lib.oracle_q1_validate.restype = C.c_int
+    lib.oracle_q1_assemble.argtypes = [i64, i64, P, P, P, d, d, d, i64, P, P, P]
+    lib.oracle_q1_assemble.restype = C.c_int
     return lib
 
 
@@ -247,3 +258,62 @@ def assemble_rows(mesh, rows, maxdeg=64, lib=None, velocity=None, rho=None, mu=N
     if st != OR_OK:
         raise ValueError(f"oracle_assemble_rows status {st}")
     return cols, deg, vals, rhs
+
+
+# ---- 2-D quadrilateral family (nsa_oracle_q1.c) ----------------------------------------------
+
+def q1_element(X, U, rho, mu, dt, rule=2, lib=None):
+    """Element matrix A [12][12] (rows test (a,c), cols trial (b,c'), dof 3a+c, c = 2 pressure) and
+    RHS [12] of a bilinear quadrilateral with the rule x rule Gauss-Legendre rule (2 is the method's)."""
+    lib = lib or load()
+    X, U = _f64(X, (4, 2)), _f64(U, (4, 2))
+    A = np.zeros((12, 12))
+    b = np.zeros(12)
+    st = lib.oracle_q1_element_rule(_p(X), _p(U), rho, mu, dt, int(rule), _p(A), _p(b))
+    if st != OR_OK:
+        raise ValueError(f"oracle_q1_element status {st}")
+    return A, b
+
+
+def q1_element_integrals(X, U, rho, mu, dt, lib=None):
+    """2x2-rule integrals of one quadrilateral: area, h, tau1, tau2, mass, stiffness, convection, aa."""
+    lib = lib or load()
+    X, U = _f64(X, (4, 2)), _f64(U, (4, 2))
+    out = dict(scal=np.zeros(4), mass=np.zeros((4, 4)), stiff=np.zeros((4, 4)), conv=np.zeros((4, 4)),
+               aa=np.zeros((4, 4)))
+    st = lib.oracle_q1_element_integrals(_p(X), _p(U), rho, mu, dt, *[_p(out[k]) for k in
+                                         ("scal", "mass", "stiff", "conv", "aa")])
+    if st != OR_OK:
+        raise ValueError(f"oracle_q1_element_integrals status {st}")
+    s = out.pop("scal")
+    out.update(area=s[0], h=s[1], tau1=s[2], tau2=s[3])
+    return out
+
+
+def q1_validate(npoin, lnods, coord, lib=None):
+    lib = lib or load()
+    ln = np.ascontiguousarray(lnods, dtype=np.int32)
+    co = _f64(coord)
+    bad = C.c_int64(-1)
+    st = lib.oracle_q1_validate(int(npoin), ln.shape[0], _p(ln), _p(co), C.byref(bad))
+    return st, bad.value
+
+
+def q1_assemble(mesh, pat=None, lib=None, rho=None, mu=None, dt=None, velocity=None):
+    """values [nnzb][3][3] and rhs [npoin][3] of a quadrilateral mesh (inputs.QuadMesh)."""
+    lib = lib or load()
+    if pat is None:
+        pat = pattern(mesh.npoin, mesh.lnods, lib=lib)
+    bptr, _, emap = pat
+    nnzb = int(bptr[-1])
+    ln = np.ascontiguousarray(mesh.lnods, dtype=np.int32)
+    vel = _f64(mesh.velocity if velocity is None else velocity)
+    values = np.zeros((nnzb, 3, 3))
+    rhs = np.zeros((mesh.npoin, 3))
+    st = lib.oracle_q1_assemble(mesh.npoin, mesh.nelem, _p(ln), _p(_f64(mesh.coord)), _p(vel),
+                                mesh.rho if rho is None else rho, mesh.mu if mu is None else mu,
+                                mesh.dt if dt is None else dt, nnzb, _p(np.ascontiguousarray(emap, dtype=np.int32)),
+                                _p(values), _p(rhs))
+    if st != OR_OK:
+        raise ValueError(f"oracle_q1_assemble status {st}")
+    return values, rhs

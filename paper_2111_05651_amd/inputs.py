@@ -332,3 +332,112 @@ def hub_mesh(level: int = 4, seed: int = 0, rho: float = 1.0, mu: float = 1e-3, 
     lnods = np.array([(0, a + 1, b + 1, c + 1) for a, b, c in faces], dtype=np.int32)
     velocity = rng.uniform(-1.0, 1.0, size=coord.shape)
     return Mesh(n=level, lnods=lnods, coord=coord, velocity=velocity, rho=rho, mu=mu, dt=dt, name=f"hub{level}")
+
+
+# ---------------------------------------------------------------------------------------------
+# 2-D family: bilinear quadrilaterals. Table 2's two 2-D benchmarks have about one element per
+# nodal point (Cylinder 2D: 1,200 elements on 1,280 points; Venturi 2D: 4,200 on 4,371) and the
+# paper states four nodes per element, so they are quadrilateral meshes. Structured unit squares
+# split into nx x ny quadrilaterals stand in for them.
+# Node ids: (i, j) -> i + (nx+1) j before renumbering; element (i, j) has the vertices
+# (i, j), (i+1, j), (i+1, j+1), (i, j+1) (counter-clockwise), elements with i fastest.
+# Random draws in this order: jitter (npoin x 2), node permutation, velocity noise.
+# ---------------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class QuadMesh:
+    """A 2-D quadrilateral mesh with a nodal velocity field and the flow parameters."""
+    nx: int
+    ny: int
+    lnods: np.ndarray         # int32 [nelem][4], counter-clockwise
+    coord: np.ndarray         # float64 [npoin][2]
+    velocity: np.ndarray      # float64 [npoin][2]
+    rho: float = 1.0
+    mu: float = 1e-3
+    dt: float = 1e-2
+    name: str = ""
+
+    @property
+    def npoin(self) -> int:
+        return int(self.coord.shape[0])
+
+    @property
+    def nelem(self) -> int:
+        return int(self.lnods.shape[0])
+
+
+def quad_grid(nx: int, ny: int):
+    """Unit-square grid of nx x ny quadrilaterals: lnods int32 [nx*ny][4], coord float64 [npoin][2]."""
+    i, j = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    coord = np.stack([i.ravel() / nx, j.ravel() / ny], axis=1).astype(np.float64)
+    ei, ej = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ei, ej = ei.ravel(), ej.ravel()
+    node = lambda a, b: a + (nx + 1) * b
+    lnods = np.stack([node(ei, ej), node(ei + 1, ej), node(ei + 1, ej + 1), node(ei, ej + 1)], axis=1)
+    return lnods.astype(np.int32), coord
+
+
+def vortex_2d(coord: np.ndarray) -> np.ndarray:
+    """Smooth 2-D vortex (sin pi x cos pi y, -cos pi x sin pi y) at the given points, [npoin][2]."""
+    px, py = math.pi * coord[:, 0], math.pi * coord[:, 1]
+    return np.stack([np.sin(px) * np.cos(py), -np.cos(px) * np.sin(py)], axis=1)
+
+
+def make_quad_mesh(nx: int, ny: int | None = None, *, jitter: bool = False, permute: bool = False,
+                   rcm: bool = False, velocity: str = "vortex", seed: int = 0, rho: float = 1.0,
+                   mu: float = 1e-3, dt: float = 1e-2, name: str = "") -> QuadMesh:
+    """Seeded quadrilateral mesh of the unit square.
+
+    jitter   every node coordinate moves by U[-0.2h, 0.2h] per component (h the cell size in that
+             direction): every quadrilateral stays convex and counter-clockwise.
+    permute  random relabelling of the nodes; rcm: then reverse Cuthill-McKee renumbering.
+    velocity "vortex": vortex_2d plus 0.01 U[-1,1]^2; "uniform": U[-1,1]^2; "zero".
+    """
+    ny = nx if ny is None else ny
+    rng = np.random.default_rng(seed)
+    lnods, coord = quad_grid(nx, ny)
+    npoin = coord.shape[0]
+    if jitter:
+        coord = coord + rng.uniform(-0.2, 0.2, size=(npoin, 2)) * np.array([1.0 / nx, 1.0 / ny])
+    if permute:
+        perm = rng.permutation(npoin)
+        new_coord = np.empty_like(coord)
+        new_coord[perm] = coord
+        coord = new_coord
+        lnods = perm[lnods].astype(np.int32)
+    if velocity == "vortex":
+        vel = vortex_2d(coord) + 0.01 * rng.uniform(-1.0, 1.0, size=(npoin, 2))
+    elif velocity == "uniform":
+        vel = rng.uniform(-1.0, 1.0, size=(npoin, 2))
+    elif velocity == "zero":
+        vel = np.zeros((npoin, 2))
+    else:
+        raise ValueError(f"unknown velocity field {velocity!r}")
+    if rcm:
+        new_id = node_graph_rcm(lnods, npoin)
+        new_coord = np.empty_like(coord)
+        new_coord[new_id] = coord
+        new_vel = np.empty_like(vel)
+        new_vel[new_id] = vel
+        coord, vel = new_coord, new_vel
+        lnods = new_id[lnods].astype(np.int32)
+    return QuadMesh(nx=nx, ny=ny, lnods=np.ascontiguousarray(lnods, dtype=np.int32),
+                    coord=np.ascontiguousarray(coord, dtype=np.float64),
+                    velocity=np.ascontiguousarray(vel, dtype=np.float64), rho=rho, mu=mu, dt=dt, name=name)
+
+
+def config_cylinder2d() -> QuadMesh:
+    """Stand-in for Cylinder 2D (1,200 elements, 1,280 points): 40 x 30 quadrilaterals, 1,271 points."""
+    return make_quad_mesh(40, 30, jitter=True, permute=True, seed=11, name="quad40x30")
+
+
+def config_venturi2d() -> QuadMesh:
+    """Stand-in for Venturi 2D (4,200 elements, 4,371 points): 70 x 60 quadrilaterals, 4,331 points."""
+    return make_quad_mesh(70, 60, jitter=True, permute=True, seed=12, name="quad70x60")
+
+
+def config_quad2048() -> QuadMesh:
+    """A 2-D throughput case: 2048 x 2048 quadrilaterals (4,194,304 elements), jittered, permuted then
+    RCM-renumbered."""
+    return make_quad_mesh(2048, jitter=True, permute=True, rcm=True, seed=13, rho=1.0, mu=1e-3, dt=5e-3,
+                          name="quad2048_rcm")
