@@ -81,6 +81,11 @@ typedef int32_t nsa_status;
                                   precomputed list of element contributions (element order) and
                                   stored once; no atomics, bit-reproducible in either scatter mode */
 
+/* element families */
+#define NSA_TET4 0             /* linear tetrahedra: 4 nodes, 3 dimensions, dofs u v w p (4x4 blocks) */
+#define NSA_QUAD4 1            /* bilinear quadrilaterals: 4 nodes, 2 dimensions, dofs u v p (3x3
+                                  blocks); Table 2's two 2-D benchmarks */
+
 /* plan indices of nsa_mesh_set_tiling beside the two scatter modes */
 #define NSA_GATHER_PLAN 2
 #define NSA_RESIDUAL_PLAN 3
@@ -145,6 +150,8 @@ typedef struct nsa_mesh_info {
     int64_t residual_records;  /* sum over tiles of the elements each tile evaluates */
     int32_t residual_tile_rows;/* requested rows per tile */
     int32_t residual_lds_bytes;/* LDS of the largest tile */
+    int32_t family;            /* NSA_TET4 or NSA_QUAD4 */
+    int32_t pad0;
 } nsa_mesh_info;
 
 typedef struct nsa_mesh nsa_mesh; /* opaque */
@@ -185,6 +192,29 @@ nsa_status nsa_pattern_fill(int64_t npoin, int64_t nelem, const int32_t *lnods, 
  * device data layout. nelem may be 0. */
 nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
                            nsa_mesh **out);
+/* The 2-D family (Table 2's Cylinder 2D and Venturi 2D: four nodes per element, about one element per
+ * nodal point): bilinear quadrilaterals. lnods host int32 [nelem][4] with the vertices of each element
+ * in counter-clockwise order (a clockwise element is accepted: the integrals use |det J|), coord host
+ * FP64 [npoin][2]. Validates the connectivity (NSA_ERANGE) and every element's Jacobian at the four
+ * Gauss points of the 2x2 rule (NSA_EDEGENERATE if it is zero, not finite or changes sign: a crossed
+ * or degenerate quadrilateral), builds the block pattern (3x3 blocks, dof 3 node + c, c = 2 pressure)
+ * and the element-to-block map. The mesh then takes nsa_mesh_set_tiling (NSA_ATOMIC, NSA_COLOUR),
+ * nsa_mesh_get_info, nsa_mesh_get_pattern, nsa_mesh_upload, nsa_mesh_release_host and nsa_assemble
+ * with vel FP64 [npoin][2], values FP64 [nnzb][3][3] and rhs FP64 [npoin][3]; the other mesh calls
+ * return NSA_EUNSUPPORTED. The element matrix integrates the same terms as for the tetrahedra with the
+ * 2x2 Gauss-Legendre rule (the Jacobian varies over a general quadrilateral), element length
+ * h = sqrt(area). */
+nsa_status nsa_mesh_create_q1(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
+                              nsa_mesh **out);
+/* Row-tile plan of a quadrilateral mesh for one scatter mode (sizes from nsa_mesh_get_info: ntiles[scatter]
+ * tiles, tile_runs[scatter] records; any array may be NULL): tile_row int32 [ntiles+1], tile_eptr int64
+ * [ntiles+1], elems int32 [records], recs [records] 48-byte records (uint16 local node ids of the four
+ * vertices in the element's order, uint16 mask of the owned vertices, uint16 0, uint16 slot[16] with
+ * slot[4a+b] the tile-local block of (vertex a, vertex b) for an owned a, 0 otherwise, two uint16 0),
+ * tile_nptr int64 [ntiles+1], tile_nodes int32 (owned rows first, then the other nodes ascending).
+ * NSA_EUNSUPPORTED for a tetrahedral mesh. */
+nsa_status nsa_mesh_get_q1_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
+                                 int32_t *elems, void *recs, int64_t *tile_nptr, int32_t *tile_nodes);
 /* Re-plan the row tiles the tiled kernel uses for one scatter mode. A tile is a contiguous range of
  * block rows whose LDS footprint (136 bytes per block, 40 per row, 48 per touched node) stays within
  * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB) and whose runs (see

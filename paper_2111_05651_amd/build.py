@@ -17,7 +17,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function",
 ]
-SOURCES = ["nsa_host.cpp", "nsa_kernels.hip", "nsa_gather.hip", "nsa_probe.hip", "nsa_static.hip"]
+SOURCES = ["nsa_host.cpp", "nsa_kernels.hip", "nsa_gather.hip", "nsa_probe.hip", "nsa_static.hip", "nsa_q1.hip"]
 
 
 def build_library(out: str = LIB, verbose: bool = False) -> str:

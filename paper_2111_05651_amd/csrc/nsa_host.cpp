@@ -1039,7 +1039,14 @@ void element_geometry(const nsa_mesh *m, int64_t e, double *g) {
     g[15] = 0.0;
 }
 
+nsa_status q1_plans(nsa_mesh *m);
+void q1_layout(nsa_mesh *m);
+
 void plan_layout(nsa_mesh *m) {
+    if (m->family == NSA_QUAD4) {
+        q1_layout(m);
+        return;
+    }
     size_t off = 0;
     auto take = [&](nsa::Region &r, size_t bytes) {
         r.off = off;
@@ -1095,6 +1102,12 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
     std::lock_guard<std::mutex> g(m->plan_mu);
     if (m->planned) return NSA_OK;
     try {
+        if (m->family == NSA_QUAD4) {
+            nsa_status st = q1_plans(m);
+            if (st) return st;
+            m->planned = true;
+            return NSA_OK;
+        }
         for (int k = 0; k < 2; k++) {
             if (m->want_blocks[k] > 0) {
                 nsa_status st = build_tiles(m, m->plan[k], m->want_blocks[k], k == 0 ? m->want_threads : kPlanThreads[k]);
@@ -1125,6 +1138,229 @@ nsa_status ensure_plans(const nsa_mesh *cm) {
 
 nsa_status hip_check(hipError_t e, const char *what) {
     if (e != hipSuccess) return fail(NSA_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return NSA_OK;
+}
+
+}  // namespace
+
+// ================================================================================================
+// 2-D family: bilinear quadrilaterals
+// ================================================================================================
+namespace {
+
+constexpr int32_t kQ1DefaultBlocks[2] = {768, 256};  // throughput plan (256 threads), one-wavefront plan
+constexpr int32_t kQ1Threads[2] = {256, 64};
+
+// det J of element e at the four Gauss points (+-1/sqrt 3)^2 of the 2x2 rule: 1 if non-zero, finite
+// and of one sign, else 0.
+int q1_element_ok(const int32_t *ln, const double *coord) {
+    static const double xi[4] = {-1.0, 1.0, 1.0, -1.0}, eta[4] = {-1.0, -1.0, 1.0, 1.0};
+    const double g = 1.0 / std::sqrt(3.0);
+    int sign = 0;
+    for (int gj = 0; gj < 2; gj++)
+        for (int gi = 0; gi < 2; gi++) {
+            const double x = gi ? g : -g, y = gj ? g : -g;
+            double J[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+            for (int a = 0; a < 4; a++) {
+                const double d0 = 0.25 * xi[a] * (1.0 + eta[a] * y), d1 = 0.25 * eta[a] * (1.0 + xi[a] * x);
+                for (int r = 0; r < 2; r++) {
+                    J[r][0] += coord[2 * (int64_t)ln[a] + r] * d0;
+                    J[r][1] += coord[2 * (int64_t)ln[a] + r] * d1;
+                }
+            }
+            const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            if (!(det != 0.0) || !std::isfinite(det)) return 0;
+            const int sg = det > 0.0 ? 1 : -1;
+            if (sign != 0 && sg != sign) return 0;
+            sign = sg;
+        }
+    return 1;
+}
+
+// Row tiles of a quadrilateral mesh: contiguous rows whose LDS (q1_lds_bytes) stays within
+// tile_blocks * 96 bytes (capped at 160 KB); one record per (element, tile) with an owned vertex.
+nsa_status build_q1_tiles(nsa_mesh *m, nsa::Q1Plan &P, int32_t tile_blocks, int32_t threads) {
+    P = nsa::Q1Plan();
+    P.tile_blocks = tile_blocks;
+    P.threads = threads;
+    const int64_t np = m->npoin;
+    if (np == 0) return NSA_OK;
+    const int64_t one_row = nsa::q1_lds_bytes((int32_t)m->max_row_blocks, 1, (int32_t)m->max_row_blocks);
+    if (one_row > kMaxTileLds || m->max_row_blocks > 4096) return NSA_OK;
+    const int64_t budget = std::max<int64_t>(std::min<int64_t>((int64_t)tile_blocks * 96, kMaxTileLds), one_row);
+    std::vector<int32_t> stamp((size_t)np, -1);
+    P.row.push_back(0);
+    int32_t tid = 0;
+    for (int64_t r0 = 0; r0 < np; tid++) {
+        int64_t r1 = r0, nodes = 0;
+        while (r1 < np) {
+            const int64_t add = row_new_nodes(m, stamp, r1, tid);
+            const int64_t blocks = m->bptr[r1 + 1] - m->bptr[r0];
+            const int64_t need = nsa::q1_lds_bytes((int32_t)blocks, (int32_t)(r1 + 1 - r0), (int32_t)(nodes + add));
+            if (r1 > r0 && (need > budget || blocks > 65535 || nodes + add > 65535)) break;
+            stamp_row(m, stamp, r1, tid);
+            nodes += add;
+            r1++;
+        }
+        P.row.push_back((int32_t)r1);
+        P.lds = std::max<int64_t>(P.lds, nsa::q1_lds_bytes((int32_t)(m->bptr[r1] - m->bptr[r0]), (int32_t)(r1 - r0),
+                                                          (int32_t)nodes));
+        r0 = r1;
+    }
+    std::vector<int32_t>().swap(stamp);
+    const int64_t nt = (int64_t)P.row.size() - 1;
+    std::vector<int64_t> n2e_ptr;
+    std::vector<int32_t> n2e;
+    node_elements(np, m->nelem, m->lnods.data(), n2e_ptr, n2e);
+    P.b0.resize((size_t)nt + 1);
+    for (int64_t t = 0; t <= nt; t++) P.b0[(size_t)t] = m->bptr[P.row[(size_t)t]];
+    P.nptr.assign(1, 0);
+    P.eptr.assign(1, 0);
+    std::vector<int32_t> els, other;
+    for (int64_t t = 0; t < nt; t++) {
+        const int32_t r0 = P.row[(size_t)t], r1 = P.row[(size_t)t + 1], nr = r1 - r0;
+        els.clear();
+        for (int32_t i = r0; i < r1; i++) els.insert(els.end(), n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
+        std::sort(els.begin(), els.end());
+        els.erase(std::unique(els.begin(), els.end()), els.end());
+        other.clear();
+        for (int32_t e : els)
+            for (int a = 0; a < 4; a++) {
+                const int32_t g = m->lnods[4 * (int64_t)e + a];
+                if (g < r0 || g >= r1) other.push_back(g);
+            }
+        // a row that no element touches is still owned (it has no blocks to write but an RHS row)
+        std::sort(other.begin(), other.end());
+        other.erase(std::unique(other.begin(), other.end()), other.end());
+        for (int32_t i = r0; i < r1; i++) P.nodes.push_back(i);
+        P.nodes.insert(P.nodes.end(), other.begin(), other.end());
+        P.nptr.push_back(P.nptr.back() + nr + (int64_t)other.size());
+        auto local = [&](int32_t g) -> uint16_t {
+            if (g >= r0 && g < r1) return (uint16_t)(g - r0);
+            return (uint16_t)(nr + (std::lower_bound(other.begin(), other.end(), g) - other.begin()));
+        };
+        const int64_t b0 = P.b0[(size_t)t];
+        for (int32_t e : els) {
+            nsa::Q1Rec r{};
+            for (int a = 0; a < 4; a++) {
+                const int32_t g = m->lnods[4 * (int64_t)e + a];
+                r.loc[a] = local(g);
+                if (g >= r0 && g < r1) {
+                    r.own |= (uint16_t)(1u << a);
+                    for (int b = 0; b < 4; b++) r.slot[4 * a + b] = (uint16_t)(m->emap[16 * (int64_t)e + 4 * a + b] - b0);
+                }
+            }
+            P.recs.push_back(r);
+            P.elems.push_back(e);
+        }
+        P.eptr.push_back((int64_t)P.recs.size());
+    }
+    P.ok = true;
+    return NSA_OK;
+}
+
+void q1_layout(nsa_mesh *m) {
+    size_t off = 0;
+    auto take = [&](nsa::Region &r, size_t bytes) {
+        r.off = off;
+        r.bytes = bytes;
+        off = align_up(off + bytes);
+    };
+    take(m->r_coord2, 2 * (size_t)m->npoin * sizeof(double));
+    for (nsa::Q1Plan &P : m->qplan) {
+        take(P.r_row, P.ok ? P.row.size() * sizeof(int32_t) : 0);
+        take(P.r_b0, P.ok ? P.b0.size() * sizeof(int64_t) : 0);
+        take(P.r_nptr, P.ok ? P.nptr.size() * sizeof(int64_t) : 0);
+        take(P.r_nodes, P.ok ? P.nodes.size() * sizeof(int32_t) : 0);
+        take(P.r_eptr, P.ok ? P.eptr.size() * sizeof(int64_t) : 0);
+        take(P.r_recs, P.ok ? P.recs.size() * sizeof(nsa::Q1Rec) : 0);
+    }
+    m->ws_bytes = std::max<size_t>(off, 256);
+}
+
+nsa_status q1_upload(nsa_mesh *m, char *w, hipStream_t s) {
+    try {
+        struct Up { const nsa::Region &r; const void *src; };
+        std::vector<Up> ups = {{m->r_coord2, m->coord.data()}};
+        for (const nsa::Q1Plan &P : m->qplan) {
+            if (!P.ok) continue;
+            ups.push_back({P.r_row, P.row.data()});
+            ups.push_back({P.r_b0, P.b0.data()});
+            ups.push_back({P.r_nptr, P.nptr.data()});
+            ups.push_back({P.r_nodes, P.nodes.data()});
+            ups.push_back({P.r_eptr, P.eptr.data()});
+            ups.push_back({P.r_recs, P.recs.data()});
+        }
+        for (const Up &u : ups) {
+            if (!u.r.bytes) continue;
+            nsa_status st = hip_check(hipMemcpyAsync(w + u.r.off, u.src, u.r.bytes, hipMemcpyHostToDevice, s), "upload copy");
+            if (st) return st;
+        }
+        nsa_status st = hip_check(hipStreamSynchronize(s), "upload sync");
+        if (st) return st;
+        int dev = -1;
+        st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+        if (st) return st;
+        m->ws = w;
+        m->device = dev;
+    } catch (const std::bad_alloc &) {
+        return fail(NSA_ENOMEM, "upload: host allocation failed");
+    }
+    return ok();
+}
+
+nsa_status q1_assemble(const nsa_mesh *m, const double *vel, double rho, double mu, double dt, const nsa_options &o,
+                       double *values, double *rhs, hipStream_t s) {
+    if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED)
+        return fail(NSA_EUNSUPPORTED, "quadrilateral meshes take the tiled kernel only");
+    if (o.err_out) return fail(NSA_EUNSUPPORTED, "err_out is not available for quadrilateral meshes");
+    const nsa::Q1Plan &P = m->qplan[o.scatter];
+    if (!P.ok && m->npoin > 0) return fail(NSA_EUNSUPPORTED, "no tile plan for this scatter mode");
+    if (o.block_threads != 0 && o.block_threads != P.threads)
+        return fail(NSA_EINVAL, "block_threads %d: this plan runs with %d", o.block_threads, P.threads);
+    if (!(rho > 0.0) || !std::isfinite(rho) || !(mu >= 0.0) || !std::isfinite(mu) || !(dt > 0.0) || !std::isfinite(dt))
+        return fail(NSA_EINVAL, "need rho > 0, mu >= 0, dt > 0 (finite); got %g %g %g", rho, mu, dt);
+    if ((m->nelem > 0 && !vel) || (m->nnzb > 0 && !values) || (m->npoin > 0 && !rhs))
+        return fail(NSA_EINVAL, "nsa_assemble: null device array");
+    if (((uintptr_t)values | (uintptr_t)rhs | (uintptr_t)vel) % 8) return fail(NSA_EINVAL, "arrays must be 8-byte aligned");
+    int dev = -1;
+    nsa_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev != m->device) return fail(NSA_EINVAL, "mesh uploaded on device %d, current device is %d", m->device, dev);
+    if (m->npoin == 0) return ok();
+    nsa::Q1Args a;
+    a.ntiles = P.ntiles();
+    a.lds_bytes = P.lds;
+    a.tile_row = (const int32_t *)(m->ws + P.r_row.off);
+    a.tile_b0 = (const int64_t *)(m->ws + P.r_b0.off);
+    a.tile_nptr = (const int64_t *)(m->ws + P.r_nptr.off);
+    a.tile_nodes = (const int32_t *)(m->ws + P.r_nodes.off);
+    a.tile_eptr = (const int64_t *)(m->ws + P.r_eptr.off);
+    a.recs = (const uint4 *)(m->ws + P.r_recs.off);
+    a.coord = (const double2 *)(m->ws + m->r_coord2.off);
+    a.vel = vel;
+    a.rho = rho;
+    a.mu = mu;
+    a.dt = dt;
+    a.accumulate = o.accumulate;
+    a.threads = P.threads;
+    a.values = values;
+    a.rhs = rhs;
+    st = hip_check(nsa::launch_q1(o.precision == NSA_MIXED ? nsa::TileKern::Mixed : nsa::TileKern::F64, a, s),
+                   "assemble (quadrilaterals)");
+    return st ? st : ok();
+}
+
+nsa_status q1_plans(nsa_mesh *m) {
+    for (int k = 0; k < 2; k++) {
+        if (m->want_blocks[k] > 0) {
+            nsa_status st = build_q1_tiles(m, m->qplan[k], m->want_blocks[k], kQ1Threads[k]);
+            if (st) return st;
+        } else {
+            m->qplan[k] = nsa::Q1Plan();
+        }
+    }
+    q1_layout(m);
     return NSA_OK;
 }
 
@@ -1254,8 +1490,83 @@ nsa_status nsa_mesh_create(int64_t npoin, int64_t nelem, const int32_t *lnods, c
     return ok();
 }
 
+nsa_status nsa_mesh_create_q1(int64_t npoin, int64_t nelem, const int32_t *lnods, const double *coord,
+                              nsa_mesh **out) {
+    if (!out || npoin < 0 || nelem < 0 || (nelem > 0 && !lnods) || (npoin > 0 && !coord))
+        return fail(NSA_EINVAL, "nsa_mesh_create_q1: bad arguments");
+    if (nelem > INT32_MAX || npoin > INT32_MAX) return fail(NSA_EUNSUPPORTED, "more than 2^31-1 nodes or elements");
+    *out = nullptr;
+    nsa_mesh *m = nullptr;
+    try {
+        nsa_status st = check_range(npoin, nelem, lnods);
+        if (st) return st;
+        std::atomic<int64_t> bad{-1};
+        parallel_for(nelem, [&](int64_t b, int64_t e) {
+            for (int64_t i = b; i < e; i++)
+                if (!q1_element_ok(lnods + 4 * i, coord)) {
+                    int64_t cur = bad.load();
+                    while ((cur < 0 || i < cur) && !bad.compare_exchange_weak(cur, i)) {
+                    }
+                }
+        });
+        if (bad.load() >= 0)
+            return fail(NSA_EDEGENERATE, "quadrilateral %lld: det J zero, not finite or of changing sign at its Gauss points",
+                        (long long)bad.load());
+        m = new nsa_mesh;
+        m->family = NSA_QUAD4;
+        m->npoin = npoin;
+        m->nelem = nelem;
+        m->keep_direct = false;
+        m->lnods.assign(lnods, lnods + 4 * nelem);
+        m->coord.assign(coord, coord + 2 * npoin);
+        std::vector<int64_t> ptr;
+        std::vector<int32_t> list;
+        node_elements(npoin, nelem, lnods, ptr, list);
+        pattern_rows(npoin, lnods, ptr, list, m->bptr, nullptr);
+        m->nnzb = m->bptr[npoin];
+        if (m->nnzb > INT32_MAX) {
+            delete m;
+            return fail(NSA_EUNSUPPORTED, "more than 2^31-1 blocks");
+        }
+        m->bcol.resize(m->nnzb);
+        pattern_rows(npoin, lnods, ptr, list, m->bptr, &m->bcol);
+        for (int64_t i = 0; i < npoin; i++)
+            m->max_row_blocks = std::max(m->max_row_blocks, m->bptr[i + 1] - m->bptr[i]);
+        m->emap.resize(16 * (size_t)nelem);
+        fill_emap(nelem, lnods, m->bptr.data(), m->bcol.data(), m->emap.data());
+        m->want_blocks[0] = kQ1DefaultBlocks[0];
+        m->want_blocks[1] = kQ1DefaultBlocks[1];
+    } catch (const std::bad_alloc &) {
+        delete m;
+        return fail(NSA_ENOMEM, "nsa_mesh_create_q1: host allocation failed");
+    }
+    *out = m;
+    return ok();
+}
+
+nsa_status nsa_mesh_get_q1_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_eptr,
+                                 int32_t *elems, void *recs, int64_t *tile_nptr, int32_t *tile_nodes) {
+    if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_q1_tiles: null mesh");
+    if (m->family != NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "nsa_mesh_get_q1_tiles: not a quadrilateral mesh");
+    if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
+    if (m->host_released) return fail(NSA_ESTATE, "host copy released");
+    nsa_status st = ensure_plans(m);
+    if (st) return st;
+    const nsa::Q1Plan &P = m->qplan[scatter];
+    if (!P.ok) return fail(NSA_EUNSUPPORTED, "no tile plan for scatter mode %d", scatter);
+    if (tile_row) std::copy(P.row.begin(), P.row.end(), tile_row);
+    if (tile_eptr) std::copy(P.eptr.begin(), P.eptr.end(), tile_eptr);
+    if (elems) std::copy(P.elems.begin(), P.elems.end(), elems);
+    if (recs) std::memcpy(recs, P.recs.data(), P.recs.size() * sizeof(nsa::Q1Rec));
+    if (tile_nptr) std::copy(P.nptr.begin(), P.nptr.end(), tile_nptr);
+    if (tile_nodes) std::copy(P.nodes.begin(), P.nodes.end(), tile_nodes);
+    return ok();
+}
+
 nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_set_tiling: null mesh");
+    if (m->family == NSA_QUAD4 && (scatter == NSA_GATHER_PLAN || scatter == NSA_RESIDUAL_PLAN))
+        return fail(NSA_EUNSUPPORTED, "quadrilateral meshes have row-tile plans for NSA_ATOMIC and NSA_COLOUR only");
     if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR && scatter != NSA_GATHER_PLAN && scatter != NSA_RESIDUAL_PLAN)
         return fail(NSA_EINVAL, "unknown plan %d", scatter);
     if (scatter == NSA_RESIDUAL_PLAN) {
@@ -1292,6 +1603,7 @@ nsa_status nsa_mesh_set_tiling(nsa_mesh *m, int32_t scatter, int32_t tile_blocks
 nsa_status nsa_mesh_set_tile_threads(nsa_mesh *m, int32_t threads) {
     if (!m || (threads != 64 && threads != 128 && threads != 192 && threads != 256))
         return fail(NSA_EINVAL, "nsa_mesh_set_tile_threads: threads must be 64, 128, 192 or 256");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_tile_threads after upload");
     std::lock_guard<std::mutex> g(m->plan_mu);
     if (m->want_threads != threads) {
@@ -1303,6 +1615,7 @@ nsa_status nsa_mesh_set_tile_threads(nsa_mesh *m, int32_t threads) {
 
 nsa_status nsa_mesh_keep_direct(nsa_mesh *m, int32_t keep) {
     if (!m || (keep != 0 && keep != 1)) return fail(NSA_EINVAL, "nsa_mesh_keep_direct: bad arguments");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_keep_direct after upload");
     std::lock_guard<std::mutex> g(m->plan_mu);
     if (m->keep_direct != (keep == 1)) {
@@ -1314,6 +1627,7 @@ nsa_status nsa_mesh_keep_direct(nsa_mesh *m, int32_t keep) {
 
 nsa_status nsa_mesh_set_residual_geometry(nsa_mesh *m, int32_t cached) {
     if (!m || (cached != 0 && cached != 1)) return fail(NSA_EINVAL, "nsa_mesh_set_residual_geometry: bad arguments");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->ws || m->host_released) return fail(NSA_ESTATE, "nsa_mesh_set_residual_geometry after upload");
     std::lock_guard<std::mutex> g(m->plan_mu);
     if (m->res_geo_cached != (cached == 1)) {
@@ -1334,6 +1648,8 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
         nsa_status st = ensure_plans(m);
         if (st) return st;
     }
+    info->family = m->family;
+    info->pad0 = 0;
     info->npoin = m->npoin;
     info->nelem = m->nelem;
     info->nnzb = m->nnzb;
@@ -1350,6 +1666,16 @@ nsa_status nsa_mesh_get_info(const nsa_mesh *m, nsa_mesh_info *info) {
         info->tile_max_runs[k] = P.cap_runs;
         info->tile_lds_bytes[k] = P.ok ? (int32_t)P.lds : 0;
     }
+    if (m->family == NSA_QUAD4)
+        for (int k = 0; k < 2; k++) {
+            const nsa::Q1Plan &Q = m->qplan[k];
+            info->ntiles[k] = Q.ntiles();
+            info->tile_runs[k] = Q.ok ? (int64_t)Q.recs.size() : 0;  // (element, tile) records
+            info->tile_blocks[k] = Q.tile_blocks;
+            info->tile_threads[k] = Q.threads;
+            info->tile_max_runs[k] = 0;
+            info->tile_lds_bytes[k] = Q.ok ? (int32_t)Q.lds : 0;
+        }
     const nsa::GatherPlan &G = m->gplan;
     info->gather_ntiles = G.ntiles();
     info->gather_records = G.ok ? G.eptr.back() : 0;
@@ -1377,6 +1703,7 @@ nsa_status nsa_mesh_get_pattern(const nsa_mesh *m, int64_t *bptr, int32_t *bcol,
 
 nsa_status nsa_pattern_scalar_csr(const nsa_mesh *m, int64_t *row_ptr, int32_t *col) {
     if (!m) return fail(NSA_EINVAL, "nsa_pattern_scalar_csr: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     if (4 * m->npoin > INT32_MAX) return fail(NSA_EUNSUPPORTED, "scalar columns exceed int32");
     if (row_ptr) {
@@ -1403,6 +1730,7 @@ nsa_status nsa_pattern_scalar_csr(const nsa_mesh *m, int64_t *row_ptr, int32_t *
 
 nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_t *colour_elems) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_colouring: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     if (colour_ptr) std::copy(m->colour_ptr.begin(), m->colour_ptr.end(), colour_ptr);
     if (colour_elems) std::copy(m->colour_elems.begin(), m->colour_elems.end(), colour_elems);
@@ -1412,6 +1740,7 @@ nsa_status nsa_mesh_get_colouring(const nsa_mesh *m, int32_t *colour_ptr, int32_
 nsa_status nsa_mesh_get_tiles(const nsa_mesh *m, int32_t scatter, int32_t *tile_row, int64_t *tile_rptr,
                               int32_t *run_elems, int64_t *tile_nptr, int32_t *tile_nodes, uint8_t *runs) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_tiles: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (scatter != NSA_ATOMIC && scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", scatter);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     nsa_status st = ensure_plans(m);
@@ -1431,6 +1760,7 @@ nsa_status nsa_mesh_get_gather(const nsa_mesh *m, int32_t *tile_row, int64_t *ti
                                int64_t *tile_eptr, int32_t *elems, uint16_t *local_nodes, int64_t *tile_pptr,
                                uint16_t *pairs, uint32_t *slots) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_gather: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     nsa_status st = ensure_plans(m);
     if (st) return st;
@@ -1451,6 +1781,7 @@ nsa_status nsa_mesh_get_gather(const nsa_mesh *m, int32_t *tile_row, int64_t *ti
 nsa_status nsa_mesh_get_residual_tiles(const nsa_mesh *m, int32_t *tile_row, int64_t *tile_eptr, int32_t *elems,
                                        uint16_t *local_nodes, int64_t *tile_nptr, int32_t *tile_nodes) {
     if (!m) return fail(NSA_EINVAL, "nsa_mesh_get_residual_tiles: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (m->host_released) return fail(NSA_ESTATE, "host copy released");
     nsa_status st = ensure_plans(m);
     if (st) return st;
@@ -1476,6 +1807,7 @@ nsa_status nsa_mesh_upload(nsa_mesh *m, void *ws, size_t ws_bytes, void *stream)
         return fail(NSA_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, m->ws_bytes);
     if (((uintptr_t)ws) % 256) return fail(NSA_EINVAL, "workspace not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
+    if (m->family == NSA_QUAD4) return q1_upload(m, (char *)ws, s);
     const int64_t ne = m->nelem, np = m->npoin;
     try {
         const bool d = m->keep_direct;
@@ -1636,6 +1968,7 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
         o.kernel != NSA_KERNEL_GATHER)
         return fail(NSA_EINVAL, "unknown kernel %d", o.kernel);
     if ((uintptr_t)o.err_out % 8) return fail(NSA_EINVAL, "err_out must be 8-byte aligned");
+    if (m->family == NSA_QUAD4) return q1_assemble(m, vel, rho, mu, dt, o, values, rhs, (hipStream_t)stream);
     const nsa::TilePlan &P = m->plan[o.scatter];
     const nsa::GatherPlan &G = m->gplan;
     if (o.kernel == NSA_KERNEL_TILED && !P.ok)
@@ -1822,6 +2155,9 @@ namespace {
 
 nsa_status check_members(int32_t nmesh, const nsa_mesh *const *meshes, int32_t scatter, int64_t *tiles, int *dev,
                          int32_t *threads) {
+    for (int32_t i = 0; i < nmesh; i++)
+        if (meshes[i] && meshes[i]->family == NSA_QUAD4)
+            return fail(NSA_EUNSUPPORTED, "the batched forms take tetrahedral meshes only (member %d)", i);
     *tiles = 0;
     *dev = -1;
     *threads = 0;
@@ -2158,6 +2494,7 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
                                  const nsa_options *opt, double *rhsid, double *dt_rho, double *mass_rho,
                                  void *stream) {
     if (!m) return fail(NSA_EINVAL, "nsa_assemble_residual: null mesh");
+    if (m->family == NSA_QUAD4) return fail(NSA_EUNSUPPORTED, "%s is not available for quadrilateral meshes", __func__);
     if (!m->ws) return fail(NSA_ESTATE, "nsa_assemble_residual: mesh not uploaded");
     nsa_options o{};
     if (opt) o = *opt;

@@ -266,6 +266,61 @@ struct ResPlan {
     int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
 };
 
+// ---- 2-D family: bilinear quadrilaterals (four nodes, two dimensions, dofs u v p, 3x3 blocks) ----
+// Row tiles as for the tetrahedra: tile t owns the contiguous rows [row[t], row[t+1]) and their blocks
+// [b0[t], b0[t+1]); its node table holds the owned rows first (local ids 0 .. nrows-1), then the other
+// nodes its elements touch, ascending. One record per (element, tile) with an owned vertex, 48 bytes
+// (Q1Rec): the element's four local node ids in its own (counter-clockwise) vertex order, a mask of
+// the owned vertices and, for owned vertex a and every vertex b, the tile-local slot of block (a, b).
+struct Q1Rec {
+    uint16_t loc[4];
+    uint16_t own, pad0;
+    uint16_t slot[16];   // slot[4a + b]; 0 where vertex a is not owned
+    uint16_t pad1[2];
+};
+static_assert(sizeof(Q1Rec) == 48, "Q1 record layout");
+
+struct Q1Args {
+    int64_t ntiles = 0;
+    int64_t lds_bytes = 0;
+    const int32_t *tile_row = nullptr;   // [ntiles+1]
+    const int64_t *tile_b0 = nullptr;    // [ntiles+1] first block of each tile (bptr at its first row)
+    const int64_t *tile_nptr = nullptr;  // [ntiles+1]
+    const int32_t *tile_nodes = nullptr;
+    const int64_t *tile_eptr = nullptr;  // [ntiles+1]
+    const uint4 *recs = nullptr;         // Q1Rec as 3 x uint4
+    const double2 *coord = nullptr;      // [npoin] (x, y)
+    const double *vel = nullptr;         // [npoin][2]
+    double rho = 1, mu = 0, dt = 1;
+    int32_t accumulate = 0;
+    int32_t threads = 256;
+    double *values = nullptr;            // [nnzb][3][3]
+    double *rhs = nullptr;               // [npoin][3]
+};
+// LDS of a quadrilateral tile: block image (9 doubles per block), RHS rows (3 doubles), node table
+// (x, y, u, v per node) at a 16-byte aligned offset.
+__host__ __device__ constexpr int64_t q1_racc_off(int32_t nblk) { return 9 * (int64_t)nblk; }
+__host__ __device__ constexpr int64_t q1_nodes_off(int32_t nblk, int32_t nrows) {
+    return (q1_racc_off(nblk) + 3 * (int64_t)nrows + 1) & ~int64_t(1);
+}
+__host__ __device__ constexpr int64_t q1_lds_bytes(int32_t nblk, int32_t nrows, int32_t nnod) {
+    return 8 * (q1_nodes_off(nblk, nrows) + 4 * (int64_t)nnod);
+}
+hipError_t launch_q1(TileKern k, const Q1Args &a, hipStream_t s);
+
+struct Q1Plan {
+    int32_t tile_blocks = 0;
+    int32_t threads = 256;
+    bool ok = false;
+    int64_t lds = 0;
+    std::vector<int32_t> row;     // [ntiles+1]
+    std::vector<int64_t> b0, nptr, eptr;
+    std::vector<int32_t> nodes, elems;
+    std::vector<Q1Rec> recs;
+    Region r_row, r_b0, r_nptr, r_nodes, r_eptr, r_recs;
+    int64_t ntiles() const { return ok ? (int64_t)row.size() - 1 : 0; }
+};
+
 // A row-tile plan for one scatter mode (host copy, then device regions after upload).
 struct TilePlan {
     int32_t tile_blocks = 0;     // requested tile size: LDS budget tile_blocks * 160 bytes
@@ -288,13 +343,14 @@ struct TilePlan {
 }  // namespace nsa
 
 struct nsa_mesh {
+    int32_t family = NSA_TET4;          // NSA_TET4 or NSA_QUAD4
     int64_t npoin = 0, nelem = 0, nnzb = 0;
     int32_t ncolours = 0;
     int64_t max_row_blocks = 0;
     bool host_released = false;
     // host copies
     std::vector<int32_t> lnods;         // [nelem][4]
-    std::vector<double> coord;          // [npoin][3]
+    std::vector<double> coord;          // [npoin][3] ([npoin][2] for quadrilateral meshes)
     std::vector<int64_t> bptr;          // [npoin+1]
     std::vector<int32_t> bcol;          // [nnzb]
     std::vector<int32_t> emap;          // [nelem][16]
@@ -307,6 +363,8 @@ struct nsa_mesh {
     int32_t want_threads = 256;         // workgroup size of the throughput plan
     nsa::GatherPlan gplan;              // gather tiles (both scatter modes, both precisions)
     int32_t want_gather = 0;
+    nsa::Q1Plan qplan[2];               // quadrilateral meshes: row tiles per scatter mode
+    nsa::Region r_coord2;               // quadrilateral meshes: coordinates (x, y)
     nsa::ResPlan rplan;                 // residual tiles (explicit-residual outputs)
     int32_t want_res = 0;
     bool res_geo_cached = false;        // residual path reads precomputed element geometry

@@ -28,7 +28,7 @@ EXPORTS = ["nsa_status_string", "nsa_last_error", "nsa_version", "nsa_pattern_co
            "nsa_mesh_get_colouring", "nsa_pattern_scalar_csr", "nsa_mesh_get_tiles", "nsa_mesh_get_gather", "nsa_mesh_upload", "nsa_mesh_release_host", "nsa_assemble",
            "nsa_batch_create", "nsa_batch_reserve", "nsa_batch_reset", "nsa_batch_destroy", "nsa_batch_get_info", "nsa_batch_upload", "nsa_batch_set_inputs",
            "nsa_assemble_batched", "nsa_assemble_batched_static", "nsa_fill_uniform", "nsa_bandwidth_probe", "nsa_mesh_get_residual_tiles", "nsa_assemble_residual",
-           "nsa_mesh_set_residual_geometry"]
+           "nsa_mesh_set_residual_geometry", "nsa_mesh_create_q1", "nsa_mesh_get_q1_tiles"]
 
 
 class NsaError(RuntimeError):
@@ -44,6 +44,7 @@ class Options(C.Structure):
 
 
 ERR_CLASSES = ("uu", "up", "pu", "pp", "rhs_u", "rhs_p")  # the classes of nsa_options.err_out
+TET4, QUAD4 = 0, 1  # element families (nsa_mesh_info.family)
 
 
 class MeshInfo(C.Structure):
@@ -55,7 +56,7 @@ class MeshInfo(C.Structure):
                 ("gather_pairs", C.c_int64), ("gather_tile_blocks", C.c_int32), ("gather_threads", C.c_int32),
                 ("gather_lds_bytes", C.c_int32 * 2), ("residual_ntiles", C.c_int64),
                 ("residual_records", C.c_int64), ("residual_tile_rows", C.c_int32),
-                ("residual_lds_bytes", C.c_int32)]
+                ("residual_lds_bytes", C.c_int32), ("family", C.c_int32), ("pad0", C.c_int32)]
 
 
 _lib = None
@@ -105,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.nsa_mesh_get_residual_tiles.argtypes = [P, P, P, P, P, P, P]
     lib.nsa_assemble_residual.argtypes = [P, P, d, d, d, C.POINTER(Options), P, P, P, P]
     lib.nsa_mesh_set_residual_geometry.argtypes = [P, i32]
+    lib.nsa_mesh_create_q1.argtypes = [i64, i64, P, P, C.POINTER(P)]
+    lib.nsa_mesh_get_q1_tiles.argtypes = [P, i32, P, P, P, P, P, P]
     for name in EXPORTS:
         if name not in ("nsa_status_string", "nsa_last_error", "nsa_version"):
             getattr(lib, name).restype = i32
@@ -170,14 +173,16 @@ class Mesh:
     def __init__(self, lnods: np.ndarray, coord: np.ndarray, tile_blocks: int | None = None,
                  tile_blocks_colour: int | None = None, keep_direct: bool = True,
                  tile_blocks_gather: int | None = None, tile_rows_residual: int | None = None,
-                 tile_threads: int | None = None, residual_geometry: bool = False):
+                 tile_threads: int | None = None, residual_geometry: bool = False, family: int = TET4):
         lib = load()
         ln = np.ascontiguousarray(lnods, dtype=np.int32)
         co = np.ascontiguousarray(coord, dtype=np.float64)
-        if ln.ndim != 2 or ln.shape[1] != 4 or co.ndim != 2 or co.shape[1] != 3:
-            raise ValueError("lnods must be [nelem][4] and coord [npoin][3]")
+        dim = 3 if family == TET4 else 2
+        if ln.ndim != 2 or ln.shape[1] != 4 or co.ndim != 2 or co.shape[1] != dim:
+            raise ValueError(f"lnods must be [nelem][4] and coord [npoin][{dim}]")
         h = C.c_void_p()
-        _check(lib.nsa_mesh_create(co.shape[0], ln.shape[0], _ptr(ln), _ptr(co), C.byref(h)), "nsa_mesh_create")
+        create = lib.nsa_mesh_create if family == TET4 else lib.nsa_mesh_create_q1
+        _check(create(co.shape[0], ln.shape[0], _ptr(ln), _ptr(co), C.byref(h)), "nsa_mesh_create")
         self._h = h
         self.ws = None
         if tile_blocks is not None:
@@ -203,6 +208,24 @@ class Mesh:
                     residual_geometry: bool = False) -> "Mesh":
         return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, keep_direct, tile_blocks_gather,
                    tile_rows_residual, tile_threads, residual_geometry)
+
+    @classmethod
+    def from_quads(cls, m, tile_blocks: int | None = None, tile_blocks_colour: int | None = None) -> "Mesh":
+        """A quadrilateral mesh (the 2-D family; inputs.QuadMesh or any object with lnods and coord [npoin][2])."""
+        return cls(m.lnods, m.coord, tile_blocks, tile_blocks_colour, family=QUAD4)
+
+    @property
+    def family(self) -> int:
+        return self.info.family
+
+    @property
+    def ndofn(self) -> int:
+        """Dofs per node: 4 (u, v, w, p) for tetrahedra, 3 (u, v, p) for quadrilaterals."""
+        return 4 if self.info.family == TET4 else 3
+
+    @property
+    def ndime(self) -> int:
+        return 3 if self.info.family == TET4 else 2
 
     def set_tiling(self, tile_blocks: int, scatter: int = ATOMIC):
         _check(load().nsa_mesh_set_tiling(self._h, int(scatter), int(tile_blocks)), "nsa_mesh_set_tiling")
@@ -273,6 +296,26 @@ class Mesh:
                "nsa_mesh_get_tiles")
         return out
 
+    Q1_REC_DTYPE = np.dtype([("loc", np.uint16, (4,)), ("own", np.uint16), ("pad0", np.uint16),
+                             ("slot", np.uint16, (16,)), ("pad1", np.uint16, (2,))])
+
+    def q1_tiles(self, scatter: int = ATOMIC):
+        """Row-tile plan of a quadrilateral mesh: dict of tile_row, tile_eptr, elems, recs (Q1_REC_DTYPE),
+        tile_nptr and tile_nodes."""
+        i = self.info
+        nt, nr = i.ntiles[scatter], i.tile_runs[scatter]
+        out = dict(tile_row=np.zeros(nt + 1, np.int32), tile_eptr=np.zeros(nt + 1, np.int64),
+                   elems=np.zeros(nr, np.int32), recs=np.zeros(nr, self.Q1_REC_DTYPE),
+                   tile_nptr=np.zeros(nt + 1, np.int64))
+        lib = load()
+        _check(lib.nsa_mesh_get_q1_tiles(self._h, int(scatter), None, None, None, None, _ptr(out["tile_nptr"]), None),
+               "nsa_mesh_get_q1_tiles")
+        out["tile_nodes"] = np.zeros(int(out["tile_nptr"][-1]), np.int32)
+        _check(lib.nsa_mesh_get_q1_tiles(self._h, int(scatter), _ptr(out["tile_row"]), _ptr(out["tile_eptr"]),
+                                         _ptr(out["elems"]), _ptr(out["recs"]), None, _ptr(out["tile_nodes"])),
+               "nsa_mesh_get_q1_tiles")
+        return out
+
     def gather(self):
         """Gather plan: dict of tile_row, tile_nptr, tile_nodes, tile_eptr, elems, local_nodes
         (uint16 [records][4]), tile_pptr, pairs (uint16) and slots (uint32 [nnzb])."""
@@ -323,8 +366,9 @@ class Mesh:
 
     def alloc_outputs(self, device="cuda"):
         import torch
-        values = torch.empty((self.nnzb, 4, 4), dtype=torch.float64, device=device)
-        rhs = torch.empty((self.npoin, 4), dtype=torch.float64, device=device)
+        k = self.ndofn
+        values = torch.empty((self.nnzb, k, k), dtype=torch.float64, device=device)
+        rhs = torch.empty((self.npoin, k), dtype=torch.float64, device=device)
         return values, rhs
 
     def __del__(self):
@@ -352,9 +396,10 @@ def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP6
     dev = mesh.ws.device
     if values is None or rhs is None:
         values, rhs = mesh.alloc_outputs(dev)
-    pv = _dev_tensor(vel, (mesh.npoin, 3), "vel", dev)
-    pval = _dev_tensor(values, (mesh.nnzb, 4, 4), "values", dev)
-    prhs = _dev_tensor(rhs, (mesh.npoin, 4), "rhs", dev)
+    k = mesh.ndofn
+    pv = _dev_tensor(vel, (mesh.npoin, mesh.ndime), "vel", dev)
+    pval = _dev_tensor(values, (mesh.nnzb, k, k), "values", dev)
+    prhs = _dev_tensor(rhs, (mesh.npoin, k), "rhs", dev)
     o = make_options(precision, scatter, accumulate, block_threads, kernel)
     if err_out is not None:
         o.err_out = _dev_tensor(err_out, (12,), "err_out", dev)

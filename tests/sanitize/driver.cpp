@@ -189,7 +189,80 @@ static void exercise(const Mesh &m) {
     }
 }
 
+// Quadrilateral meshes: an n x n grid of the unit square with every node moved a little (seeded), its
+// nodes relabelled by a fixed permutation; create, both row-tile plans, every record's indices.
+void exercise_q1(int n, int tile_blocks) {
+    const int64_t np = (int64_t)(n + 1) * (n + 1), ne = (int64_t)n * n;
+    std::vector<int64_t> perm((size_t)np);
+    for (int64_t i = 0; i < np; i++) perm[(size_t)i] = (i * 7919) % np;  // a bijection: 7919 is prime, np < 7919^2
+    bool bij = true;
+    {
+        std::vector<char> hit((size_t)np, 0);
+        for (int64_t i = 0; i < np; i++) hit[(size_t)perm[(size_t)i]]++;
+        for (char c : hit) bij = bij && c == 1;
+    }
+    if (!bij)
+        for (int64_t i = 0; i < np; i++) perm[(size_t)i] = i;
+    std::vector<double> coord(2 * (size_t)np);
+    uint64_t z = 12345;
+    for (int j = 0; j <= n; j++)
+        for (int i = 0; i <= n; i++) {
+            const int64_t id = perm[(size_t)(i + (n + 1) * j)];
+            z = z * 6364136223846793005ull + 1442695040888963407ull;
+            const double jx = ((double)(z >> 11) * 0x1.0p-53 - 0.5) * 0.3 / n;
+            z = z * 6364136223846793005ull + 1442695040888963407ull;
+            const double jy = ((double)(z >> 11) * 0x1.0p-53 - 0.5) * 0.3 / n;
+            coord[2 * id] = (double)i / n + jx;
+            coord[2 * id + 1] = (double)j / n + jy;
+        }
+    std::vector<int32_t> ln(4 * (size_t)ne);
+    for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+            const int64_t e = i + (int64_t)n * j;
+            const int64_t v[4] = {i + (int64_t)(n + 1) * j, i + 1 + (int64_t)(n + 1) * j, i + 1 + (int64_t)(n + 1) * (j + 1),
+                                  i + (int64_t)(n + 1) * (j + 1)};
+            for (int a = 0; a < 4; a++) ln[4 * e + a] = (int32_t)perm[(size_t)v[a]];
+        }
+    nsa_mesh *h = nullptr;
+    CHECK(nsa_mesh_create_q1(np, ne, ln.data(), coord.data(), &h) == NSA_OK, "q1 create: %s", nsa_last_error());
+    if (!h) return;
+    CHECK(nsa_mesh_set_tiling(h, NSA_ATOMIC, tile_blocks) == NSA_OK, "q1 tiling");
+    nsa_mesh_info info;
+    CHECK(nsa_mesh_get_info(h, &info) == NSA_OK && info.family == NSA_QUAD4, "q1 info");
+    std::vector<int64_t> bptr((size_t)np + 1);
+    std::vector<int32_t> bcol((size_t)info.nnzb), emap(16 * (size_t)ne);
+    CHECK(nsa_mesh_get_pattern(h, bptr.data(), bcol.data(), emap.data()) == NSA_OK, "q1 pattern");
+    for (int sc = 0; sc < 2; sc++) {
+        const int64_t nt = info.ntiles[sc], nr = info.tile_runs[sc];
+        std::vector<int32_t> row((size_t)nt + 1), elems((size_t)nr);
+        std::vector<int64_t> eptr((size_t)nt + 1), nptr((size_t)nt + 1);
+        std::vector<uint16_t> recs(24 * (size_t)nr);
+        CHECK(nsa_mesh_get_q1_tiles(h, sc, nullptr, nullptr, nullptr, nullptr, nptr.data(), nullptr) == NSA_OK, "q1 nptr");
+        std::vector<int32_t> nodes((size_t)nptr[(size_t)nt]);
+        CHECK(nsa_mesh_get_q1_tiles(h, sc, row.data(), eptr.data(), elems.data(), recs.data(), nptr.data(), nodes.data()) ==
+                  NSA_OK, "q1 tiles");
+        for (int64_t t = 0; t < nt; t++) {
+            const int64_t nblk = bptr[(size_t)row[(size_t)t + 1]] - bptr[(size_t)row[(size_t)t]];
+            const int64_t nnod = nptr[(size_t)t + 1] - nptr[(size_t)t];
+            for (int64_t p = eptr[(size_t)t]; p < eptr[(size_t)t + 1]; p++) {
+                const uint16_t *r = &recs[24 * (size_t)p];
+                for (int a = 0; a < 4; a++) {
+                    CHECK(r[a] < nnod, "q1 local id");
+                    CHECK(nodes[(size_t)(nptr[(size_t)t] + r[a])] == ln[4 * (size_t)elems[(size_t)p] + a], "q1 node");
+                    if ((r[4] >> a) & 1)
+                        for (int b = 0; b < 4; b++) CHECK(r[6 + 4 * a + b] < nblk, "q1 slot");
+                }
+            }
+        }
+    }
+    nsa_mesh_destroy(h);
+}
+
 int main(int argc, char **argv) {
+    exercise_q1(1, 64);
+    exercise_q1(17, 64);
+    exercise_q1(40, 768);
+    std::printf("quadrilateral meshes done\n");
     for (int k = 1; k < argc; k++) {
         Mesh m;
         if (!read_mesh(argv[k], m)) {

@@ -20,7 +20,7 @@ def lib():
 def header_functions():
     src = open(os.path.join(ROOT, "include", "nsa.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nsa_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(nsa_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(lib):
