@@ -123,15 +123,17 @@ def host_description():
     return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
-def class_diff(a_values, a_rhs, b_values, b_rhs):
-    """Per block class {uu, up, pu, pp} and RHS class {u, p}: max|a - b| / max|b|."""
+def class_diff(a_values, a_rhs, b_values, b_rhs, ndofn=4):
+    """Per block class {uu, up, pu, pp} and RHS class {u, p}: max|a - b| / max|b| (pressure is the last
+    of the ndofn dofs of a node: 4 for tetrahedra, 3 for quadrilaterals)."""
+    q = ndofn - 1
     out = {}
-    sl = {"uu": (slice(0, 3), slice(0, 3)), "up": (slice(0, 3), slice(3, 4)), "pu": (slice(3, 4), slice(0, 3)),
-          "pp": (slice(3, 4), slice(3, 4))}
+    sl = {"uu": (slice(0, q), slice(0, q)), "up": (slice(0, q), slice(q, q + 1)), "pu": (slice(q, q + 1), slice(0, q)),
+          "pp": (slice(q, q + 1), slice(q, q + 1))}
     for k, (i, j) in sl.items():
         ref = b_values[:, i, j]
         out[k] = float((a_values[:, i, j] - ref).abs().max() / ref.abs().max())
-    for k, c in (("rhs_u", slice(0, 3)), ("rhs_p", slice(3, 4))):
+    for k, c in (("rhs_u", slice(0, q)), ("rhs_p", slice(q, q + 1))):
         ref = b_rhs[:, c]
         den = ref.abs().max()
         out[k] = float((a_rhs[:, c] - ref).abs().max() / den) if den > 0 else float((a_rhs[:, c] - ref).abs().max())
@@ -282,6 +284,78 @@ def run_residual(args, m, prec):
     print(json.dumps(line), flush=True)
 
 
+def run_quads(args, prec):
+    """The 2-D family: bilinear quadrilaterals (block-CSR with 3x3 blocks plus RHS)."""
+    import torch
+    import oracle
+    from paper_2111_05651_amd import inputs, nsa
+    t0 = time.perf_counter()
+    m = {"quad2048": inputs.config_quad2048, "cylinder2d": inputs.config_cylinder2d,
+         "venturi2d": inputs.config_venturi2d}[args.workload]()
+    log(f"workload {args.workload}: {m.nelem} quadrilaterals, {m.npoin} nodes ({time.perf_counter() - t0:.1f} s)")
+    scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
+    mesh = nsa.Mesh.from_quads(m).upload("cuda:0")
+    info = mesh.info
+    log(f"mesh registered: nnzb={info.nnzb} ntiles={info.ntiles[scat]} records/nelem="
+        f"{info.tile_runs[scat] / max(m.nelem, 1):.2f} lds={info.tile_lds_bytes[scat]}")
+    vel = torch.from_numpy(m.velocity).to("cuda:0")
+    values, rhs = mesh.alloc_outputs("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step(p=prec):
+        nsa.assemble(mesh, vel, m.rho, m.mu, m.dt, precision=p, scatter=scat, values=values, rhs=rhs, stream=stream)
+
+    est, _, _ = time_steps(step, 3, 1, stream)
+    series = timing_series(step, stream, est, seconds=args.series_seconds)
+    log(f"timing series: {series['launches']} launches, median {series['median_ms']:.4f} ms, min {series['min_ms']:.4f} ms")
+    ms, _, _ = time_steps(step, args.steps, args.warmup, stream)
+    beside = None
+    if not args.no_beside:
+        other = nsa.FP64 if prec == nsa.MIXED else nsa.MIXED
+        fv, fr = values.clone(), rhs.clone()
+        ms_o, _, _ = time_steps(lambda: step(other), args.steps, args.warmup, stream)
+        series_o = timing_series(lambda: step(other), stream, ms_o, seconds=args.series_seconds)
+        if other == nsa.MIXED:
+            diff = class_diff(values, rhs, fv, fr, ndofn=3)
+        else:
+            diff = class_diff(fv, fr, values, rhs, ndofn=3)
+        beside = {"precision": "mixed" if other == nsa.MIXED else "fp64", "value": m.nelem / (ms_o / 1e3),
+                  "ms_per_step": ms_o, "unit": "elements/s", "same_gpu": True, "timing": series_o,
+                  "mixed_vs_fp64_class_error": diff}
+        log(f"{beside['precision']} beside it: {ms_o:.4f} ms/step; class errors {diff}")
+    # what the method must move: connectivity, coordinates + velocity (2 + 2 doubles per node), every
+    # 3x3 block written once, the RHS (3 doubles per node)
+    nbytes = 16 * m.nelem + 32 * m.npoin + 72 * info.nnzb + 24 * m.npoin
+    launch_ms = series["mean_ms"]
+    achieved = nbytes / (launch_ms / 1e3) / 1e9
+    rt = "float" if prec == nsa.MIXED else "double"
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None, "kernel": f"k_q1<{rt},{info.tile_threads[scat]}>",
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": launch_ms,
+            "launch_ms_basis": f"mean of the {series['launches']} launches of the timing series"}
+    line = {"metric": "elements assembled/s", "value": m.nelem / (ms / 1e3), "unit": "elements/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if prec == nsa.MIXED else "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {m.name}", "family": "bilinear quadrilaterals",
+                       "nelem": m.nelem, "npoin": m.npoin, "nnzb": info.nnzb, "precision": args.precision,
+                       "scatter": args.scatter, "rho": m.rho, "mu": m.mu, "dt": m.dt},
+            "hbm_GBs": achieved, "timing": series, "roofline": roof, "beside": beside}
+    if not args.no_cpu_baseline:
+        nsample = min(m.nelem, args.cpu_sample or 1_000_000)
+        sub = inputs.QuadMesh(nx=m.nx, ny=m.ny, lnods=m.lnods[:nsample].copy(), coord=m.coord, velocity=m.velocity,
+                              rho=m.rho, mu=m.mu, dt=m.dt)
+        pat = oracle.pattern(sub.npoin, sub.lnods)
+        t0 = time.perf_counter()
+        oracle.q1_assemble(sub, pat)
+        t = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": nsample / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                                "sample": f"first {nsample} elements of the same mesh, serial FP64 C oracle "
+                                          f"(nsa_oracle_q1.c, {t:.1f} s); pattern build untimed",
+                                **host_description()}
+    print(json.dumps(line), flush=True)
+
+
 def traffic_for(kernel_key, launches_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on this
     exact kernel source and configuration; else None."""
@@ -303,6 +377,8 @@ def run_batch(args):
     import torch
     from paper_2111_05651_amd import autotune, inputs, nsa
     prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
+    if args.workload in ("quad2048", "cylinder2d", "venturi2d"):
+        return run_quads(args, prec)
     scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
     t0 = time.perf_counter()
     ms_ = inputs.config_batch()
@@ -557,7 +633,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube128", choices=["cube128", "cube64", "cube8", "batch64", "serve"])
+    ap.add_argument("--workload", default="cube128",
+                    choices=["cube128", "cube64", "cube8", "batch64", "serve", "quad2048", "cylinder2d", "venturi2d"])
     ap.add_argument("--precision", default=None, choices=["mixed", "fp64"],
                     help="default: fp64 for the single-mesh workloads (mixed timed beside), mixed for batch64 "
                          "and serve (compared against plain FP64 launches)")
@@ -623,6 +700,8 @@ def main():
     if args.workload == "serve":
         return run_serve(args)
     prec = {"mixed": nsa.MIXED, "fp64": nsa.FP64}[args.precision]
+    if args.workload in ("quad2048", "cylinder2d", "venturi2d"):
+        return run_quads(args, prec)
     scat = {"atomic": nsa.ATOMIC, "colour": nsa.COLOUR}[args.scatter]
     kern = {"tiled": nsa.KERNEL_TILED, "direct": nsa.KERNEL_DIRECT, "auto": nsa.KERNEL_AUTO,
             "gather": nsa.KERNEL_GATHER}[args.kernel]
