@@ -1,10 +1,24 @@
-// Device helpers shared by the assembly kernels: FP64 reciprocal and inverse cube root, and the
-// FP64 geometry of a linear tetrahedron.
+// Device helpers shared by the assembly kernels: streaming loads and stores, FP64 reciprocal and
+// inverse cube root, and the FP64 geometry of a linear tetrahedron.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace nsa {
+
+// Streaming accesses (the nt bit): data read or written once per launch -- a tile's run records,
+// its block-image write-out -- so that it does not displace the node data that neighbouring tiles
+// read again from L2.
+typedef double stream_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned stream_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_stream(double2 *p, double2 v) {
+    __builtin_nontemporal_store((stream_d2){v.x, v.y}, reinterpret_cast<stream_d2 *>(p));
+}
+__device__ __forceinline__ void store_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ uint4 load_stream(const uint4 *p) {
+    const stream_u4 t = __builtin_nontemporal_load(reinterpret_cast<const stream_u4 *>(p));
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
 
 // Reciprocal: hardware estimate refined by two Newton steps (full FP64 accuracy for normal x).
 __device__ __forceinline__ double fast_rcp(double x) {

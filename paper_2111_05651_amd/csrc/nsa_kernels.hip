@@ -677,8 +677,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     int64_t p = p0 + tid;
     uint4 h = make_uint4(0u, 0u, 0u, 0u), kk = h;
     if (p < p1) {
-        h = A.runs[2 * p];
-        kk = A.runs[2 * p + 1];
+        h = load_stream(A.runs + 2 * p);
+        kk = load_stream(A.runs + 2 * p + 1);
     }
     if (first && tid < nnod) {
         double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * tid);
@@ -708,8 +708,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
         tile_run<R, NL>(A, rdt, h, kk, acc, racc, nodes);
         p += NT;
         if (p < p1) {
-            h = A.runs[2 * p];
-            kk = A.runs[2 * p + 1];
+            h = load_stream(A.runs + 2 * p);
+            kk = load_stream(A.runs + 2 * p + 1);
         }
     }
     __syncthreads();
@@ -724,7 +724,7 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
             v.x += o.x;
             v.y += o.y;
         }
-        out[i] = v;
+        store_stream(out + i, v);
     }
     double *rout = A.rhs + 4 * (int64_t)r0;
     for (int i = tid; i < 4 * nrows; i += NT) {

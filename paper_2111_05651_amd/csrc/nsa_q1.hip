@@ -191,14 +191,14 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
     const double rdt = A.rho / A.dt;
     for (int64_t p = p0 + tid; p < p1; p += NT) {
         const uint4 *rp = A.recs + 3 * p;
-        q1_element<R>(A, rdt, rp[0], rp[1], rp[2], nodes, acc, racc);
+        q1_element<R>(A, rdt, load_stream(rp), load_stream(rp + 1), load_stream(rp + 2), nodes, acc, racc);
     }
     __syncthreads();
     double *out = A.values + 9 * b0;
     for (int i = tid; i < 9 * nblk; i += NT) {
         double v = acc[i];
         if (A.accumulate) v += out[i];
-        out[i] = v;
+        store_stream(out + i, v);
     }
     double *rout = A.rhs + 3 * (int64_t)r0;
     for (int i = tid; i < 3 * nrows; i += NT) {
