@@ -12,7 +12,7 @@
 // block rows, stages its nodes (x, y, u, v) in LDS, adds the contributions of its owned rows into an
 // FP64 LDS image of its blocks with ds_add_f64 and writes the image to HBM once, coalesced. One lane
 // takes one (element, tile) record and integrates the element's owned rows; the throughput plan runs
-// a tile on 256 threads, the deterministic plan on one wavefront, whose LDS adds come in program order.
+// a tile on two wavefronts, the deterministic plan on one wavefront, whose LDS adds come in program order.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -222,6 +222,7 @@ hipError_t launch_q1(TileKern k, const Q1Args &a, hipStream_t s) {
     };
     const bool mixed = k == TileKern::Mixed;
     if (a.threads == 64) return mixed ? go(k_q1<float, 64>, 64) : go(k_q1<double, 64>, 64);
+    if (a.threads == 128) return mixed ? go(k_q1<float, 128>, 128) : go(k_q1<double, 128>, 128);
     return mixed ? go(k_q1<float, 256>, 256) : go(k_q1<double, 256>, 256);
 }
 
