@@ -655,6 +655,10 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const ui
 template <typename R, int NT, int NL>
 __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double *smem) {
     const int tid = threadIdx.x;
+    // Throughput plan: the prologue runs at raised wave priority, so that its gathers issue ahead of
+    // the element code of the CU's other workgroup and the tile starts sooner (128^3: -4 %). The
+    // one-wavefront tiles of the deterministic plan, six per CU, lose with it.
+    if constexpr (NT > 64) __builtin_amdgcn_s_setprio(2);
     // The node ids sit at a fixed stride per tile, so the first pass of node gathers needs no tile
     // header: it is issued first and waits for one round trip (ids, then coordinates and velocities)
     // while the header loads are in flight.
@@ -702,6 +706,7 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     }
     for (int i = tid; i < kRhsStride * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();
+    if constexpr (NT > 64) __builtin_amdgcn_s_setprio(0);
     // one run per lane (a tile with more runs than lanes takes several rounds)
     const double rdt = A.rho / A.dt;
     while (p < p1) {
