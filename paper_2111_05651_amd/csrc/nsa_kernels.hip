@@ -659,14 +659,26 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     // the element code of the CU's other workgroup and the tile starts sooner (128^3: -4 %). The
     // one-wavefront tiles of the deterministic plan, six per CU, lose with it.
     if constexpr (NT > 64) __builtin_amdgcn_s_setprio(2);
-    // The node ids sit at a fixed stride per tile, so the first pass of node gathers needs no tile
-    // header: it is issued first and waits for one round trip (ids, then coordinates and velocities)
-    // while the header loads are in flight.
+    // The node ids sit at a fixed stride per tile (padded with a node of the tile), so the first
+    // kSpec passes of node gathers need no tile header: they are issued first and wait for one round
+    // trip (ids, then coordinates and velocities) while the header loads are in flight; only their
+    // LDS stores depend on the tile's node count. Two passes cover the throughput plan's tiles (about
+    // 440 nodes at 128^3); the one-wavefront tiles hold up to ~140 nodes, and four passes there measured faster
+    // than the three that cover them (128^3: mixed 1.60 -> 1.52 ms, FP64 1.59 -> 1.57 ms).
+    constexpr int kSpec = NT == 64 ? 4 : 2;
     const int32_t *nid = A.tile_npad + tile * A.cap_nodes;
-    const bool first = tid < A.cap_nodes;
-    const int64_t g1 = first ? nid[tid] : 0;
-    const double4 c1 = A.coord[g1];
-    const double u1 = A.vel[3 * g1], v1 = A.vel[3 * g1 + 1], w1 = A.vel[3 * g1 + 2];
+    int64_t gs[kSpec];
+#pragma unroll
+    for (int q = 0; q < kSpec; q++) gs[q] = tid + q * NT < A.cap_nodes ? nid[tid + q * NT] : 0;
+    double4 cs[kSpec];
+    double us[kSpec][3];
+#pragma unroll
+    for (int q = 0; q < kSpec; q++) {
+        cs[q] = A.coord[gs[q]];
+        us[q][0] = A.vel[3 * gs[q]];
+        us[q][1] = A.vel[3 * gs[q] + 1];
+        us[q][2] = A.vel[3 * gs[q] + 2];
+    }
     const int r0 = A.tile_row[tile], r1 = A.tile_row[tile + 1], nrows = r1 - r0;
     const int64_t b0 = A.tile_b0[tile];
     const int nblk = (int)(A.tile_b0[tile + 1] - b0);
@@ -684,13 +696,17 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
         h = load_stream(A.runs + 2 * p);
         kk = load_stream(A.runs + 2 * p + 1);
     }
-    if (first && tid < nnod) {
-        double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * tid);
-        nd[0] = make_double2(c1.x, c1.y);
-        nd[1] = make_double2(c1.z, u1);
-        nd[2] = make_double2(v1, w1);
+#pragma unroll
+    for (int q = 0; q < kSpec; q++) {
+        const int i = tid + q * NT;
+        if (i < nnod) {
+            double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
+            nd[0] = make_double2(cs[q].x, cs[q].y);
+            nd[1] = make_double2(cs[q].z, us[q][0]);
+            nd[2] = make_double2(us[q][1], us[q][2]);
+        }
     }
-    for (int i = tid + NT; i < nnod; i += NT) {
+    for (int i = tid + kSpec * NT; i < nnod; i += NT) {
         const int64_t gnode = nid[i];
         const double4 c = A.coord[gnode];
         const double *v = A.vel + 3 * gnode;
@@ -1017,14 +1033,30 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
         }
         if (p + NT < p1) en = A.rgel[p + NT];
     }
-    for (int i = tid; i < nnod; i += NT) {
-        const int64_t gnode = A.tile_nodes[n0 + i];
-        const double4 c = A.coord[gnode];
-        const double *v = A.vel + 3 * gnode;
-        double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
-        nd[0] = make_double2(c.x, c.y);
-        nd[1] = make_double2(c.z, v[0]);
-        nd[2] = make_double2(v[1], v[2]);
+    // node gathers four passes at a time: the ids, then the node data, then the LDS stores, so the
+    // passes wait for one round trip together
+    for (int i0 = tid; i0 < nnod; i0 += 4 * NT) {
+        int64_t g[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) g[u] = A.tile_nodes[n0 + min(i0 + u * NT, nnod - 1)];
+        double4 c[4];
+        double v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            c[u] = A.coord[g[u]];
+            v[u][0] = A.vel[3 * g[u]];
+            v[u][1] = A.vel[3 * g[u] + 1];
+            v[u][2] = A.vel[3 * g[u] + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (i0 + u * NT < nnod) {
+                double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * (i0 + u * NT));
+                nd[0] = make_double2(c[u].x, c[u].y);
+                nd[1] = make_double2(c[u].z, v[u][0]);
+                nd[2] = make_double2(v[u][1], v[u][2]);
+            }
+        }
     }
     for (int i = tid; i < kResStride * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();

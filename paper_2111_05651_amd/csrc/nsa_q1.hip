@@ -177,13 +177,26 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
     double *acc = smem;
     double *racc = smem + q1_racc_off(nblk);
     double *nodes = smem + q1_nodes_off(nblk, nrows);
-    for (int i = tid; i < nnod; i += NT) {
-        const int64_t g = A.tile_nodes[n0 + i];
-        const double2 c = A.coord[g];
-        const double2 v = make_double2(A.vel[2 * g], A.vel[2 * g + 1]);
-        double2 *nd = reinterpret_cast<double2 *>(nodes + 4 * i);
-        nd[0] = c;
-        nd[1] = v;
+    // node gathers two passes at a time: the ids, then the node data, then the LDS stores, so the
+    // passes wait for one round trip together
+    for (int i0 = tid; i0 < nnod; i0 += 2 * NT) {
+        int64_t g[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) g[u] = A.tile_nodes[n0 + min(i0 + u * NT, nnod - 1)];
+        double2 c[2], v[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            c[u] = A.coord[g[u]];
+            v[u] = make_double2(A.vel[2 * g[u]], A.vel[2 * g[u] + 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            if (i0 + u * NT < nnod) {
+                double2 *nd = reinterpret_cast<double2 *>(nodes + 4 * (i0 + u * NT));
+                nd[0] = c[u];
+                nd[1] = v[u];
+            }
+        }
     }
     for (int i = tid; i < 9 * nblk; i += NT) acc[i] = 0.0;
     for (int i = tid; i < 3 * nrows; i += NT) racc[i] = 0.0;
