@@ -568,7 +568,7 @@ __device__ __forceinline__ void block0(const Row0<R> &C, int b, double acc[16]) 
 // (row, k_new(q)), which element q+1 adds to again as its (row, k_old); that sum is complete after
 // element q+1 and goes into the LDS image then. Per element one block is added into LDS, per run
 // three blocks and the RHS row.
-enum NodeLoads { NL_ALL, NL_REUSE, NL_AHEAD };
+enum NodeLoads { NL_ALL, NL_AHEAD };
 
 template <typename R, int NL>
 __device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const uint4 h, const uint4 k, double *acc,
@@ -582,10 +582,10 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const ui
 #pragma unroll
     for (int c = 0; c < 4; c++) sr[c] = 0.0;
     // Node reads (NL): consecutive elements share the row, the hinge and one more node, so with
-    // NL_REUSE or NL_AHEAD each element reads one new node from the node table and keeps the others in
-    // registers; NL_AHEAD reads it one element ahead, before the current element's LDS adds (LDS
-    // operations complete in order, so a read issued after 16 adds waits for them). NL_ALL reads all
-    // four nodes per element (fewest registers).
+    // NL_AHEAD each element reads one new node from the node table and keeps the others in registers,
+    // reading it one element ahead, before the current element's LDS adds (LDS operations complete in
+    // order, so a read issued after 16 adds waits for them). NL_ALL reads all four nodes per element
+    // (fewest registers: the FP64 form keeps no node data across elements).
     constexpr bool kAhead = NL == NL_AHEAD;
     double Xr[3], Ur[3], Xh[3], Uh[3], Xo[3], Uo[3], Xn[3], Un[3];
     if (NL != NL_ALL) {
@@ -763,11 +763,11 @@ __global__ __launch_bounds__(NT, 2) void k_tiled(TileArgs A) {
     // XCD-aware order (xcd_item): runs of consecutive tiles per XCD, drawn from the whole mesh
     const int64_t tile = xcd_item(blockIdx.x);
     if (tile >= A.ntiles) return;
-    // FP64: reusing node data costs 3 spilled registers and still wins, reading ahead spills more. The
-    // one-wavefront (deterministic) form reads as the batched FP64 kernel does, so that a mesh's
-    // deterministic result is the same bits alone and batched.
+    // FP64 reads all four nodes per element: 238 registers and no spills, where keeping the shared
+    // nodes in registers spilled 5 and was 1.5 % slower at 128^3 (reading ahead spills 11). The batched
+    // FP64 kernel reads the same way, so a mesh's deterministic result is the same bits alone and batched.
     constexpr bool f64 = std::is_same<R, double>::value;
-    run_tile<R, NT, f64 ? (NT > 64 ? NL_REUSE : NL_ALL) : NL_AHEAD>(A, tile, smem);
+    run_tile<R, NT, f64 ? NL_ALL : NL_AHEAD>(A, tile, smem);
 }
 
 // Batched form: one launch over the tiles of many meshes. work[t] = (mesh, tile of that mesh) with
