@@ -405,7 +405,7 @@ def run_batch(args):
     nelem = sum(m.nelem for m in ms_)
     log(f"batch of {len(ms_)} meshes, {nelem} tets ({time.perf_counter() - t0:.1f} s)")
     tuned = autotune.tune_batch(ms_, scat, prec, cache=None, log=log,
-                                tile_candidates=(336, 384, 512) if scat == nsa.ATOMIC else (160, 256))
+                                tile_candidates=(336, 384, 512) if scat == nsa.ATOMIC else (128, 160, 256))
     log(f"autotuned: {({k: tuned[k] for k in ('tile_blocks', 'block_threads', 'grid_wgs', 'ms')})}")
     handles, b, vels, outs = autotune.build_batch(ms_, tuned["tile_blocks"], scat)
     nt = tuned["block_threads"] if scat == nsa.ATOMIC else 0
@@ -670,7 +670,7 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0, help="workgroup size override (0 = the plan's)")
     ap.add_argument("--tile-blocks", type=int, default=512, help="tile size of the atomic-mode plan")
     ap.add_argument("--tile-threads", type=int, default=0, help="workgroup size of the atomic-mode plan (0 = default)")
-    ap.add_argument("--tile-blocks-colour", type=int, default=160, help="tile size of the colour-mode plan")
+    ap.add_argument("--tile-blocks-colour", type=int, default=128, help="tile size of the colour-mode plan")
     ap.add_argument("--no-beside", action="store_true",
                     help="skip timing the other precision beside (mixed beside FP64, or FP64 beside mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

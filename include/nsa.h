@@ -219,7 +219,7 @@ nsa_status nsa_mesh_get_q1_tiles(const nsa_mesh *m, int32_t scatter, int32_t *ti
  * block rows whose LDS footprint (136 bytes per block, 40 per row, 48 per touched node) stays within
  * tile_blocks * 160 bytes (64 <= tile_blocks <= 1024; capped at 160 KB) and whose runs (see
  * nsa_mesh_get_tiles) number at most the plan's workgroup size. Defaults: 512 (NSA_ATOMIC, 256-thread
- * workgroups) and 160 (NSA_COLOUR, one wavefront per tile); tile_blocks = 0 drops the plan of that
+ * workgroups) and 128 (NSA_COLOUR, one wavefront per tile); tile_blocks = 0 drops the plan of that
  * mode (the tiled kernel then refuses the mode and NSA_KERNEL_AUTO falls back to the direct kernel).
  * Plans are built on first need (nsa_mesh_get_info, nsa_mesh_get_tiles, nsa_mesh_upload). Must be
  * called before nsa_mesh_upload (NSA_ESTATE after). */

@@ -302,7 +302,7 @@ def test_tile_plan_in_bounds(lib, scatter, tile_blocks):
 def test_tile_plan_defaults(lib):
     m = inputs.make_mesh(4, jitter=True, permute=True, seed=32)
     mesh = nsa.Mesh.from_inputs(m)
-    assert list(mesh.info.tile_blocks) == [512, 160] and list(mesh.info.tile_threads) == [256, 64]
+    assert list(mesh.info.tile_blocks) == [512, 128] and list(mesh.info.tile_threads) == [256, 64]
     for scatter in (nsa.ATOMIC, nsa.COLOUR):
         check_tile_plan(m, mesh, scatter)
     m1 = inputs.make_mesh(1, seed=33)

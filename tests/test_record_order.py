@@ -63,17 +63,24 @@ def row_order(runs):
     return np.lexsort((runs["hinge"], runs["row"], -runs["len"].astype(np.int64)))
 
 
-@pytest.mark.parametrize("scatter", [nsa.ATOMIC, nsa.COLOUR])
+# (scatter mode, deterministic tile size, bar on the shared-row excess). The one-wavefront tiles hold
+# ~10 rows at 160 blocks and ~8 at the default 128 for 16 lanes, so on a randomly numbered mesh the
+# order has fewer rows to spread a group over there (measured: 0.26 of the plain order's excess at
+# 160 blocks, 0.40 at 128; 0.13-0.14 on the RCM mesh at either size).
+PLANS = [(nsa.ATOMIC, None, 0.15), (nsa.COLOUR, 160, 0.35), (nsa.COLOUR, None, 0.45)]
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: f"{'atomic' if p[0] == nsa.ATOMIC else 'colour'}{p[1] or ''}")
 @pytest.mark.parametrize("name", ["rcm", "random"])
-def test_run_order(scatter, name):
+def test_run_order(plan, name):
+    scatter, tbc, frac = plan
     m = (inputs.make_mesh(16, jitter=True, permute=True, rcm=True, sort_elements=True, seed=61) if name == "rcm"
          else inputs.make_mesh(12, jitter=True, permute=True, seed=62))
-    mesh = nsa.Mesh.from_inputs(m)
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_colour=tbc)
     got, got_shared, bound = group_stats(mesh, scatter)
     base, base_shared, _ = group_stats(mesh, scatter, row_order)
     assert got <= 0.85 * base, (got, base)
     # lanes on a row already taken in their group: close to the least possible, far below the plain order
-    frac = 0.15 if scatter == nsa.ATOMIC else 0.35  # one-wavefront tiles have ~10 rows for 16 lanes
     assert got_shared - bound <= frac * (base_shared - bound), (got_shared, bound, base_shared)
 
 
