@@ -71,6 +71,10 @@ typedef int32_t nsa_status;
                                   with plain load-add-store and needs no such assumption, as does
                                   the gather kernel (NSA_KERNEL_GATHER) */
 
+/* velocity layout (nsa_options.vel_layout) */
+#define NSA_VEL_AOS 0          /* vel[node][d], d < the mesh's dimensions: veloc(idime, ipoin) of Listing 2 */
+#define NSA_VEL_SOA 1          /* vel[d][node]: one contiguous array of npoin values per component */
+
 /* kernel family */
 #define NSA_KERNEL_AUTO 0      /* the row-tiled kernel when the mesh allows it, else the direct one */
 #define NSA_KERNEL_TILED 1     /* row tiles: each workgroup owns contiguous block rows, reduces the
@@ -100,7 +104,10 @@ typedef struct nsa_options {
                                   the plan's, see nsa_mesh_set_tile_threads);
                                   ignored by the tiled colour mode (one wavefront per tile) */
     int32_t kernel;            /* NSA_KERNEL_AUTO, _TILED, _DIRECT or _GATHER */
-    int32_t reserved;          /* must be zero */
+    int32_t vel_layout;        /* NSA_VEL_AOS (0, the default) or NSA_VEL_SOA: how the velocity array
+                                  of nsa_assemble, nsa_assemble_residual and
+                                  nsa_assemble_batched_static is laid out; the batch handle
+                                  (nsa_assemble_batched) takes NSA_VEL_AOS only */
     double *err_out;           /* optional error report of nsa_assemble (NULL: none; the other
                                   entry points take NULL only). Device pointer to 12 doubles,
                                   8-byte aligned, written in stream order after the assembly:

@@ -20,6 +20,22 @@ __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
     return make_uint4(t.x, t.y, t.z, t.w);
 }
 
+// Velocity of node g from vel[g][d] (soa == 0) or vel[d][g] (soa = the node count), as node stride sn
+// and component stride sc: (3, 1) or (1, npoin). No branch, so the gathers of several nodes issue
+// back to back whatever the layout.
+__device__ __forceinline__ void load_vel3(const double *vel, int64_t soa, int64_t g, double &u, double &v, double &w) {
+    const int64_t sn = soa ? 1 : 3, sc = soa ? soa : 1;
+    const double *p = vel + g * sn;
+    u = p[0];
+    v = p[sc];
+    w = p[2 * sc];
+}
+__device__ __forceinline__ double2 load_vel2(const double *vel, int64_t soa, int64_t g) {
+    const int64_t sn = soa ? 1 : 2, sc = soa ? soa : 1;
+    const double *p = vel + g * sn;
+    return make_double2(p[0], p[sc]);
+}
+
 // Reciprocal: hardware estimate refined by two Newton steps (full FP64 accuracy for normal x).
 __device__ __forceinline__ double fast_rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);

@@ -166,7 +166,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_gather(GatherArgs A) {
     for (int i = tid; i < nnod; i += NT) {
         const int64_t gnode = A.tile_nodes[n0 + i];
         const double4 c = A.coord[gnode];
-        const double *v = A.vel + 3 * gnode;
+        double v[3];
+        load_vel3(A.vel, A.vel_soa, gnode, v[0], v[1], v[2]);
         double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
         nd[0] = make_double2(c.x, c.y);
         nd[1] = make_double2(c.z, v[0]);

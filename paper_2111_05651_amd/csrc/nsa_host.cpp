@@ -1344,6 +1344,7 @@ nsa_status q1_assemble(const nsa_mesh *m, const double *vel, double rho, double 
     a.recs = (const uint4 *)(m->ws + P.r_recs.off);
     a.coord = (const double2 *)(m->ws + m->r_coord2.off);
     a.vel = vel;
+    a.vel_soa = o.vel_layout == NSA_VEL_SOA ? m->npoin : 0;
     a.rho = rho;
     a.mu = mu;
     a.dt = dt;
@@ -1968,12 +1969,14 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
     if (o.scatter != NSA_ATOMIC && o.scatter != NSA_COLOUR)
         return fail(NSA_EINVAL, "unknown scatter mode %d", o.scatter);
     if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
-    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.vel_layout != NSA_VEL_AOS && o.vel_layout != NSA_VEL_SOA)
+        return fail(NSA_EINVAL, "unknown velocity layout %d", o.vel_layout);
     if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED && o.kernel != NSA_KERNEL_DIRECT &&
         o.kernel != NSA_KERNEL_GATHER)
         return fail(NSA_EINVAL, "unknown kernel %d", o.kernel);
     if ((uintptr_t)o.err_out % 8) return fail(NSA_EINVAL, "err_out must be 8-byte aligned");
     if (m->family == NSA_QUAD4) return q1_assemble(m, vel, rho, mu, dt, o, values, rhs, (hipStream_t)stream);
+    const int64_t vsoa = o.vel_layout == NSA_VEL_SOA ? m->npoin : 0;
     const nsa::TilePlan &P = m->plan[o.scatter];
     const nsa::GatherPlan &G = m->gplan;
     if (o.kernel == NSA_KERNEL_TILED && !P.ok)
@@ -2016,6 +2019,7 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
         a.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
         a.coord = (const double4 *)(m->ws + m->r_coord4.off);
         a.vel = vel;
+        a.vel_soa = vsoa;
         a.rho = rho;
         a.mu = mu;
         a.dt = dt;
@@ -2042,6 +2046,7 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
         t.bptr = (const int64_t *)(m->ws + m->r_bptr.off);
         t.coord = (const double4 *)(m->ws + m->r_coord4.off);
         t.vel = vel;
+        t.vel_soa = vsoa;
         t.rho = rho;
         t.mu = mu;
         t.dt = dt;
@@ -2068,6 +2073,7 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
     a.npoin = m->npoin;
     a.coord = (const double *)(m->ws + m->r_coord.off);
     a.vel = vel;
+    a.vel_soa = vsoa;
     a.rho = rho;
     a.mu = mu;
     a.dt = dt;
@@ -2098,14 +2104,14 @@ nsa_status assemble_impl(const nsa_mesh *m, const double *vel, double rho, doubl
 }
 
 // The err_out report: the sampled elements in the call's precision and in FP64 (see nsa_options).
-nsa_status error_report(const nsa_mesh *m, const double *vel, double rho, double mu, double dt, bool mixed,
-                        double *err, hipStream_t s) {
+nsa_status error_report(const nsa_mesh *m, const double *vel, int64_t vel_soa, double rho, double mu, double dt,
+                        bool mixed, double *err, hipStream_t s) {
     nsa_status st = hip_check(nsa::launch_fill_zero(err, 12, s), "err_out clear");
     if (st) return st;
     const int64_t ns = std::min<int64_t>(m->nelem, NSA_ERR_SAMPLE);
     if (ns == 0) return ok();
     return hip_check(nsa::launch_err_sample((const int4 *)(m->ws + m->r_esamp.off), (int)ns,
-                                            (const double4 *)(m->ws + m->r_coord4.off), vel, rho, mu, rho / dt,
+                                            (const double4 *)(m->ws + m->r_coord4.off), vel, vel_soa, rho, mu, rho / dt,
                                             mixed, err, s),
                      "err_out sample");
 }
@@ -2115,7 +2121,8 @@ nsa_status nsa_assemble(const nsa_mesh *m, const double *vel, double rho, double
                         const nsa_options *opt, double *values, double *rhs, void *stream) {
     nsa_status st = assemble_impl(m, vel, rho, mu, dt, opt, values, rhs, stream);
     if (st || !opt || !opt->err_out) return st;
-    st = error_report(m, vel, rho, mu, dt, opt->precision == NSA_MIXED, opt->err_out, (hipStream_t)stream);
+    st = error_report(m, vel, opt->vel_layout == NSA_VEL_SOA ? m->npoin : 0, rho, mu, dt, opt->precision == NSA_MIXED,
+                      opt->err_out, (hipStream_t)stream);
     return st ? st : ok();
 }
 
@@ -2254,8 +2261,9 @@ nsa_status batch_push_work(nsa_batch *b, hipStream_t s) {
 
 // Check member i's inputs and outputs and fill its descriptor (the batched form and its
 // allocation-free variant).
-nsa_status member_desc(const nsa_mesh *m, int32_t scatter, int32_t i, const double *vel, double rho, double mu,
-                       double dt, double *values, double *rhs, int32_t accumulate, int32_t threads, nsa::TileArgs &t) {
+nsa_status member_desc(const nsa_mesh *m, int32_t scatter, int32_t i, const double *vel, bool vel_soa, double rho,
+                       double mu, double dt, double *values, double *rhs, int32_t accumulate, int32_t threads,
+                       nsa::TileArgs &t) {
     const nsa::TilePlan &P = m->plan[scatter];
     if (!(rho > 0.0) || !std::isfinite(rho) || !(mu >= 0.0) || !std::isfinite(mu) || !(dt > 0.0) || !std::isfinite(dt))
         return fail(NSA_EINVAL, "mesh %d: need rho > 0, mu >= 0, dt > 0 (finite)", i);
@@ -2278,6 +2286,7 @@ nsa_status member_desc(const nsa_mesh *m, int32_t scatter, int32_t i, const doub
         t.coord = (const double4 *)(m->ws + m->r_coord4.off);
     }
     t.vel = vel;
+    t.vel_soa = vel_soa ? m->npoin : 0;
     t.rho = rho;
     t.mu = mu;
     t.dt = dt;
@@ -2381,8 +2390,8 @@ nsa_status nsa_batch_set_inputs(nsa_batch *b, const double *const *vel, const do
     nsa_status st = hip_check(hipEventSynchronize(b->copied), "batch staging wait");
     if (st) return st;
     for (size_t i = 0; i < b->meshes.size(); i++) {
-        st = member_desc(b->meshes[i], b->scatter, (int32_t)i, vel[i], rho[i], mu[i], dt[i], values[i], rhs[i], accumulate,
-                         b->threads, b->desc_host()[i]);
+        st = member_desc(b->meshes[i], b->scatter, (int32_t)i, vel[i], false, rho[i], mu[i], dt[i], values[i], rhs[i],
+                         accumulate, b->threads, b->desc_host()[i]);
         if (st) return st;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -2408,7 +2417,10 @@ nsa_status nsa_assemble_batched(const nsa_batch *b, const nsa_options *opt, int3
     if (o.precision != NSA_FP64 && o.precision != NSA_MIXED) return fail(NSA_EINVAL, "unknown precision %d", o.precision);
     if (o.scatter != b->scatter) return fail(NSA_EINVAL, "batch was built for scatter mode %d", b->scatter);
     if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
-    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.vel_layout != NSA_VEL_AOS && o.vel_layout != NSA_VEL_SOA)
+        return fail(NSA_EINVAL, "unknown velocity layout %d", o.vel_layout);
+    if (o.vel_layout != NSA_VEL_AOS)
+        return fail(NSA_EUNSUPPORTED, "the batch handle takes velocities as [npoin][3] (NSA_VEL_AOS)");
     if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     const int64_t total = b->ntiles;
     if (grid_wgs < 0) return fail(NSA_EINVAL, "grid_wgs must be >= 0");
@@ -2442,7 +2454,8 @@ nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *mes
     if (o.scatter != NSA_ATOMIC && o.scatter != NSA_COLOUR) return fail(NSA_EINVAL, "unknown scatter mode %d", o.scatter);
     if (o.kernel == NSA_KERNEL_DIRECT) return fail(NSA_EUNSUPPORTED, "the batched form uses the tiled kernel");
     if (o.accumulate != 0 && o.accumulate != 1) return fail(NSA_EINVAL, "accumulate must be 0 or 1");
-    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.vel_layout != NSA_VEL_AOS && o.vel_layout != NSA_VEL_SOA)
+        return fail(NSA_EINVAL, "unknown velocity layout %d", o.vel_layout);
     if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     int64_t total = 0;
     int mdev = -1;
@@ -2472,8 +2485,8 @@ nsa_status nsa_assemble_batched_static(int32_t nmesh, const nsa_mesh *const *mes
         c.count = std::min<int32_t>(nsa::kDescChunk, nmesh - i0);
         for (int32_t j = 0; j < c.count; j++) {
             const int32_t i = i0 + j;
-            st = member_desc(meshes[i], o.scatter, i, vel[i], rho[i], mu[i], dt[i], values[i], rhs[i], o.accumulate,
-                             plan_threads, c.d[j]);
+            st = member_desc(meshes[i], o.scatter, i, vel[i], o.vel_layout == NSA_VEL_SOA, rho[i], mu[i], dt[i],
+                             values[i], rhs[i], o.accumulate, plan_threads, c.d[j]);
             if (st) return st;
             c.toff[j] = off;
             off += c.d[j].ntiles;
@@ -2510,7 +2523,8 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
     if (o.kernel != NSA_KERNEL_AUTO && o.kernel != NSA_KERNEL_TILED)
         return fail(NSA_EUNSUPPORTED, "the residual path has the tiled kernel only");
     if (o.block_threads != 0 && o.block_threads != 256) return fail(NSA_EINVAL, "block_threads must be 0 or 256");
-    if (o.reserved) return fail(NSA_EINVAL, "reserved option fields must be zero");
+    if (o.vel_layout != NSA_VEL_AOS && o.vel_layout != NSA_VEL_SOA)
+        return fail(NSA_EINVAL, "unknown velocity layout %d", o.vel_layout);
     if (o.err_out) return fail(NSA_EINVAL, "err_out is taken by nsa_assemble only");
     const nsa::ResPlan &RP = m->rplan;
     if (!RP.ok && m->npoin > 0)
@@ -2537,6 +2551,7 @@ nsa_status nsa_assemble_residual(const nsa_mesh *m, const double *vel, double rh
     a.tile_nodes = (const int32_t *)(m->ws + RP.r_nodes.off);
     a.coord = (const double4 *)(m->ws + m->r_coord4.off);
     a.vel = vel;
+    a.vel_soa = o.vel_layout == NSA_VEL_SOA ? m->npoin : 0;
     a.rho = rho;
     a.mu = mu;
     a.dt = dt;

@@ -30,6 +30,7 @@ struct AsmArgs {
     const int32_t *emap = nullptr;
     const double *coord = nullptr;
     const double *vel = nullptr;
+    int64_t vel_soa = 0;         // 0: vel [npoin][3]; npoin: vel [3][npoin]
     double rho = 1, mu = 0, dt = 1;
     double *values = nullptr;
     double *rhs = nullptr;
@@ -43,8 +44,8 @@ hipError_t launch_assemble(Kern k, const AsmArgs &a, int threads, hipStream_t s)
 // err_out report over ns sampled elements (node ids in samp): per class the largest |value - FP64
 // value| (0 unless mixed) and the largest |FP64 value| into err[0..5] and err[6..11], which must hold
 // zeros or earlier maxima (non-negative) on entry.
-hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, double rho, double mu,
-                             double rdt, bool mixed, double *err, hipStream_t s);
+hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, int64_t vel_soa,
+                             double rho, double mu, double rdt, bool mixed, double *err, hipStream_t s);
 
 // Row tiles: tile t owns the contiguous block rows [row[t], row[t+1]) and therefore the contiguous
 // blocks [bptr[r0], bptr[r1]). Its nodes tile_nodes[nptr[t] .. nptr[t+1]) are the owned rows (local
@@ -82,7 +83,8 @@ struct TileArgs {
     int32_t cap_nodes = 0;
     const int64_t *bptr = nullptr;       // [npoin+1]
     const double4 *coord = nullptr;      // [npoin] (x, y, z, 0)
-    const double *vel = nullptr;         // [npoin][3]
+    const double *vel = nullptr;         // [npoin][3], or [3][npoin] with vel_soa = npoin
+    int64_t vel_soa = 0;
     double rho = 1, mu = 0, dt = 1;
     int32_t accumulate = 0;
     int32_t threads = 256;               // workgroup size: 64, 128 or 256
@@ -178,6 +180,7 @@ struct GatherArgs {
     const int64_t *bptr = nullptr;
     const double4 *coord = nullptr;
     const double *vel = nullptr;
+    int64_t vel_soa = 0;                 // 0: vel [npoin][3]; npoin: vel [3][npoin]
     double rho = 1, mu = 0, dt = 1;
     int32_t accumulate = 0;
     int32_t threads = 256;
@@ -235,6 +238,7 @@ struct ResArgs {
     const int32_t *tile_nodes = nullptr;
     const double4 *coord = nullptr;
     const double *vel = nullptr;
+    int64_t vel_soa = 0;                 // 0: vel [npoin][3]; npoin: vel [3][npoin]
     double rho = 1, mu = 0, dt = 1;
     int32_t accumulate = 0;
     double *rhsid = nullptr;             // [npoin][3]
@@ -290,7 +294,8 @@ struct Q1Args {
     const int64_t *tile_eptr = nullptr;  // [ntiles+1]
     const uint4 *recs = nullptr;         // Q1Rec as 3 x uint4
     const double2 *coord = nullptr;      // [npoin] (x, y)
-    const double *vel = nullptr;         // [npoin][2]
+    const double *vel = nullptr;         // [npoin][2], or [2][npoin] with vel_soa = npoin
+    int64_t vel_soa = 0;
     double rho = 1, mu = 0, dt = 1;
     int32_t accumulate = 0;
     int32_t threads = 256;

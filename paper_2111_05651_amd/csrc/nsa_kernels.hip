@@ -162,12 +162,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_assemble(AsmArgs A) {
     for (int a = 0; a < 4; a++) n[a] = A.ln[a * A.ld + e];
     double X[4][3], U[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < 4; a++) {
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            X[a][d] = A.coord[d * A.npoin + n[a]];
-            U[a][d] = A.vel[3 * (int64_t)n[a] + d];
-        }
+        for (int d = 0; d < 3; d++) X[a][d] = A.coord[d * A.npoin + n[a]];
+        load_vel3(A.vel, A.vel_soa, n[a], U[a][0], U[a][1], U[a][2]);
+    }
     Geo g;
     geometry(X, g);
     Elem<R> E;
@@ -675,9 +674,7 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
 #pragma unroll
     for (int q = 0; q < kSpec; q++) {
         cs[q] = A.coord[gs[q]];
-        us[q][0] = A.vel[3 * gs[q]];
-        us[q][1] = A.vel[3 * gs[q] + 1];
-        us[q][2] = A.vel[3 * gs[q] + 2];
+        load_vel3(A.vel, A.vel_soa, gs[q], us[q][0], us[q][1], us[q][2]);
     }
     const int r0 = A.tile_row[tile], r1 = A.tile_row[tile + 1], nrows = r1 - r0;
     const int64_t b0 = A.tile_b0[tile];
@@ -709,7 +706,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     for (int i = tid + kSpec * NT; i < nnod; i += NT) {
         const int64_t gnode = nid[i];
         const double4 c = A.coord[gnode];
-        const double *v = A.vel + 3 * gnode;
+        double v[3];
+        load_vel3(A.vel, A.vel_soa, gnode, v[0], v[1], v[2]);
         double2 *nd = reinterpret_cast<double2 *>(nodes + 6 * i);
         nd[0] = make_double2(c.x, c.y);
         nd[1] = make_double2(c.z, v[0]);
@@ -838,7 +836,7 @@ __device__ __forceinline__ int err_class(int i) {  // entry i of a 4x4 block: uu
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_err_sample(const int4 *__restrict__ samp, int ns,
                                                     const double4 *__restrict__ coord, const double *__restrict__ vel,
-                                                    double rho, double mu, double rdt, double *err) {
+                                                    int64_t vel_soa, double rho, double mu, double rdt, double *err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double md[6], mr[6];
 #pragma unroll
@@ -853,8 +851,7 @@ __global__ __launch_bounds__(256) void k_err_sample(const int4 *__restrict__ sam
             X[a][0] = c.x;
             X[a][1] = c.y;
             X[a][2] = c.z;
-#pragma unroll
-            for (int d = 0; d < 3; d++) U[a][d] = vel[3 * (int64_t)n[a] + d];
+            load_vel3(vel, vel_soa, n[a], U[a][0], U[a][1], U[a][2]);
         }
         for (int a = 0; a < 4; a++) {
             double Xa[4][3], Ua[4][3];
@@ -1044,9 +1041,7 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             c[u] = A.coord[g[u]];
-            v[u][0] = A.vel[3 * g[u]];
-            v[u][1] = A.vel[3 * g[u] + 1];
-            v[u][2] = A.vel[3 * g[u] + 2];
+            load_vel3(A.vel, A.vel_soa, g[u], v[u][0], v[u][1], v[u][2]);
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -1129,14 +1124,14 @@ hipError_t launch_tiled(TileKern k, const TileArgs &a, hipStream_t s) {
     return mixed ? go(k_tiled<float, 256>) : go(k_tiled<double, 256>);
 }
 
-hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, double rho, double mu,
-                             double rdt, bool mixed, double *err, hipStream_t s) {
+hipError_t launch_err_sample(const int4 *samp, int ns, const double4 *coord, const double *vel, int64_t vel_soa,
+                             double rho, double mu, double rdt, bool mixed, double *err, hipStream_t s) {
     if (ns <= 0) return hipSuccess;
     const dim3 grid((unsigned)((ns + 255) / 256)), block(256);
     if (mixed)
-        hipLaunchKernelGGL(k_err_sample<true>, grid, block, 0, s, samp, ns, coord, vel, rho, mu, rdt, err);
+        hipLaunchKernelGGL(k_err_sample<true>, grid, block, 0, s, samp, ns, coord, vel, vel_soa, rho, mu, rdt, err);
     else
-        hipLaunchKernelGGL(k_err_sample<false>, grid, block, 0, s, samp, ns, coord, vel, rho, mu, rdt, err);
+        hipLaunchKernelGGL(k_err_sample<false>, grid, block, 0, s, samp, ns, coord, vel, vel_soa, rho, mu, rdt, err);
     return hipGetLastError();
 }
 

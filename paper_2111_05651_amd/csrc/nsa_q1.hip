@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             c[u] = A.coord[g[u]];
-            v[u] = make_double2(A.vel[2 * g[u]], A.vel[2 * g[u] + 1]);
+            v[u] = load_vel2(A.vel, A.vel_soa, g[u]);
         }
 #pragma unroll
         for (int u = 0; u < 2; u++) {

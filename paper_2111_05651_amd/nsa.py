@@ -18,6 +18,7 @@ NSA_OK, NSA_EINVAL, NSA_ERANGE, NSA_EDEGENERATE, NSA_ENOMEM, NSA_EHIP, NSA_EUNSU
 FP64, MIXED = 0, 1
 ATOMIC, COLOUR = 0, 1
 KERNEL_AUTO, KERNEL_TILED, KERNEL_DIRECT, KERNEL_GATHER = 0, 1, 2, 3
+VEL_AOS, VEL_SOA = 0, 1  # velocity [npoin][ndime] or [ndime][npoin]
 GATHER_PLAN = 2
 PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
 RESIDUAL_PLAN = 3
@@ -39,7 +40,7 @@ class NsaError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("scatter", C.c_int32), ("accumulate", C.c_int32),
-                ("block_threads", C.c_int32), ("kernel", C.c_int32), ("reserved", C.c_int32),
+                ("block_threads", C.c_int32), ("kernel", C.c_int32), ("vel_layout", C.c_int32),
                 ("err_out", C.c_void_p)]
 
 
@@ -378,29 +379,35 @@ class Mesh:
             self._h = None
 
 
-def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads=0, kernel=KERNEL_AUTO) -> Options:
+def make_options(precision=FP64, scatter=ATOMIC, accumulate=False, block_threads=0, kernel=KERNEL_AUTO,
+                 vel_layout=VEL_AOS) -> Options:
     o = Options()
     o.precision, o.scatter, o.accumulate = int(precision), int(scatter), int(accumulate)
-    o.block_threads, o.kernel = int(block_threads), int(kernel)
+    o.block_threads, o.kernel, o.vel_layout = int(block_threads), int(kernel), int(vel_layout)
     return o
+
+
+def _vel_shape(npoin: int, ndime: int, vel_layout: int):
+    return (ndime, npoin) if vel_layout == VEL_SOA else (npoin, ndime)
 
 
 def assemble(mesh: Mesh, vel, rho: float, mu: float, dt: float, *, precision=FP64, scatter=ATOMIC,
              accumulate=False, block_threads=0, kernel=KERNEL_AUTO, values=None, rhs=None, err_out=None,
-             stream=None):
+             vel_layout=VEL_AOS, stream=None):
     """Launch nsa_assemble on the stream (default: torch's current stream); returns (values, rhs)
-    as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given). err_out: optional
-    float64 device tensor of 12 entries for the library's error report (see error_report)."""
+    as device tensors [nnzb][4][4] and [npoin][4] (allocated if not given). vel: [npoin][ndime], or
+    [ndime][npoin] with vel_layout=VEL_SOA. err_out: optional float64 device tensor of 12 entries for
+    the library's error report (see error_report)."""
     if mesh.ws is None:
         raise ValueError("the mesh has not been uploaded (Mesh.upload)")
     dev = mesh.ws.device
     if values is None or rhs is None:
         values, rhs = mesh.alloc_outputs(dev)
     k = mesh.ndofn
-    pv = _dev_tensor(vel, (mesh.npoin, mesh.ndime), "vel", dev)
+    pv = _dev_tensor(vel, _vel_shape(mesh.npoin, mesh.ndime, vel_layout), "vel", dev)
     pval = _dev_tensor(values, (mesh.nnzb, k, k), "values", dev)
     prhs = _dev_tensor(rhs, (mesh.npoin, k), "rhs", dev)
-    o = make_options(precision, scatter, accumulate, block_threads, kernel)
+    o = make_options(precision, scatter, accumulate, block_threads, kernel, vel_layout)
     if err_out is not None:
         o.err_out = _dev_tensor(err_out, (12,), "err_out", dev)
     _check(load().nsa_assemble(mesh._h, pv, float(rho), float(mu), float(dt), C.byref(o), pval, prhs,
@@ -416,7 +423,7 @@ def error_report(err_out) -> dict:
 
 
 def assemble_residual(mesh: Mesh, vel, rho, mu, dt, precision=FP64, accumulate=False, rhsid=None, dt_rho=None,
-                      mass_rho=None, stream=None):
+                      mass_rho=None, vel_layout=VEL_AOS, stream=None):
     """Explicit-residual outputs (rhsid [npoin][3], dt_rho [npoin], mass_rho [npoin]) on the device;
     outputs are allocated when not given."""
     import torch
@@ -429,9 +436,10 @@ def assemble_residual(mesh: Mesh, vel, rho, mu, dt, precision=FP64, accumulate=F
         dt_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
     if mass_rho is None:
         mass_rho = torch.empty(mesh.npoin, dtype=torch.float64, device=dev)
-    ptrs = (_dev_tensor(vel, (mesh.npoin, 3), "vel", dev), _dev_tensor(rhsid, (mesh.npoin, 3), "rhsid", dev),
+    ptrs = (_dev_tensor(vel, _vel_shape(mesh.npoin, 3, vel_layout), "vel", dev),
+            _dev_tensor(rhsid, (mesh.npoin, 3), "rhsid", dev),
             _dev_tensor(dt_rho, (mesh.npoin,), "dt_rho", dev), _dev_tensor(mass_rho, (mesh.npoin,), "mass_rho", dev))
-    o = make_options(precision, ATOMIC, accumulate)
+    o = make_options(precision, ATOMIC, accumulate, vel_layout=vel_layout)
     _check(load().nsa_assemble_residual(mesh._h, ptrs[0], float(rho), float(mu), float(dt), C.byref(o), *ptrs[1:],
                                         _stream_handle(stream)), "nsa_assemble_residual")
     return rhsid, dt_rho, mass_rho
@@ -464,11 +472,12 @@ def bandwidth_probe(kind: int, src=None, dst=None, stream=None):
 
 
 def assemble_batched_static(meshes, vels, rho, mu, dt, outputs, precision=MIXED, scatter=ATOMIC, accumulate=False,
-                            block_threads=0, stream=None):
+                            block_threads=0, vel_layout=VEL_AOS, stream=None):
     """The batched form without a batch handle or workspace (nsa_assemble_batched_static): one launch
     over every tile of the uploaded meshes, the tables in the library's fixed per-GPU device array.
     No device allocation. At most 256 meshes and 2^20 tiles; calls that overlap on one GPU race.
-    vels: device tensors [npoin][3]; rho, mu, dt: sequences; outputs: [(values, rhs), ...]."""
+    vels: device tensors [npoin][3] ([3][npoin] with vel_layout=VEL_SOA); rho, mu, dt: sequences;
+    outputs: [(values, rhs), ...]."""
     meshes, vels, outputs = list(meshes), list(vels), list(outputs)
     n = len(meshes)
     if not (len(vels) == len(outputs) == len(rho) == len(mu) == len(dt) == n):
@@ -477,7 +486,8 @@ def assemble_batched_static(meshes, vels, rho, mu, dt, outputs, precision=MIXED,
     hs = (P * n)(*[m._h.value for m in meshes])
     if any(m.ws is None for m in meshes):
         raise ValueError("assemble_batched_static: every mesh must be uploaded (Mesh.upload)")
-    v = (P * n)(*[_dev_tensor(x, (m.npoin, 3), f"vels[{i}]", m.ws.device) for i, (x, m) in enumerate(zip(vels, meshes))])
+    v = (P * n)(*[_dev_tensor(x, _vel_shape(m.npoin, 3, vel_layout), f"vels[{i}]", m.ws.device)
+                  for i, (x, m) in enumerate(zip(vels, meshes))])
     va = (P * n)(*[_dev_tensor(o[0], (m.nnzb, 4, 4), f"outputs[{i}][0]", m.ws.device)
                    for i, (o, m) in enumerate(zip(outputs, meshes))])
     ra = (P * n)(*[_dev_tensor(o[1], (m.npoin, 4), f"outputs[{i}][1]", m.ws.device)
@@ -485,7 +495,7 @@ def assemble_batched_static(meshes, vels, rho, mu, dt, outputs, precision=MIXED,
     dr = (C.c_double * n)(*[float(x) for x in rho])
     dm = (C.c_double * n)(*[float(x) for x in mu])
     dd = (C.c_double * n)(*[float(x) for x in dt])
-    o = make_options(precision, scatter, accumulate=accumulate, block_threads=block_threads)
+    o = make_options(precision, scatter, accumulate=accumulate, block_threads=block_threads, vel_layout=vel_layout)
     _check(load().nsa_assemble_batched_static(n, hs, v, dr, dm, dd, va, ra, C.byref(o), _stream_handle(stream)),
            "nsa_assemble_batched_static")
 

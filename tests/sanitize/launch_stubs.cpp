@@ -16,8 +16,8 @@ hipError_t ensure_lds(const void *, size_t) { return hipErrorNotSupported; }
 hipError_t launch_gather(TileKern, const GatherArgs &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_residual(TileKern, const ResArgs &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_q1(TileKern, const Q1Args &, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_err_sample(const int4 *, int, const double4 *, const double *, double, double, double, bool, double *,
-                             hipStream_t) {
+hipError_t launch_err_sample(const int4 *, int, const double4 *, const double *, int64_t, double, double, double, bool,
+                             double *, hipStream_t) {
     return hipErrorNotSupported;
 }
 hipError_t launch_probe(int, const double *, double *, int64_t, int, hipStream_t) { return hipErrorNotSupported; }
