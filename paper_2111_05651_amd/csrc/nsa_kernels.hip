@@ -656,14 +656,15 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     const int tid = threadIdx.x;
     // Throughput plan: the prologue runs at raised wave priority, so that its gathers issue ahead of
     // the element code of the CU's other workgroup and the tile starts sooner (128^3: -4 %). The
-    // one-wavefront tiles of the deterministic plan, six per CU, lose with it.
+    // one-wavefront tiles of the deterministic plan, eight per CU, lose with it.
     if constexpr (NT > 64) __builtin_amdgcn_s_setprio(2);
     // The node ids sit at a fixed stride per tile (padded with a node of the tile), so the first
     // kSpec passes of node gathers need no tile header: they are issued first and wait for one round
     // trip (ids, then coordinates and velocities) while the header loads are in flight; only their
     // LDS stores depend on the tile's node count. Two passes cover the throughput plan's tiles (about
-    // 440 nodes at 128^3); the one-wavefront tiles hold up to ~140 nodes, and four passes there measured faster
-    // than the three that cover them (128^3: mixed 1.60 -> 1.52 ms, FP64 1.59 -> 1.57 ms).
+    // 440 nodes at 128^3). The one-wavefront tiles hold at most ~140 nodes, yet four passes measured
+    // faster there than the three that cover them (128^3, 160-block tiles: mixed 1.60 -> 1.52 ms,
+    // FP64 1.59 -> 1.57 ms).
     constexpr int kSpec = NT == 64 ? 4 : 2;
     const int32_t *nid = A.tile_npad + tile * A.cap_nodes;
     int64_t gs[kSpec];
