@@ -575,11 +575,17 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const ui
     const int row = (int)(h.x & 0xffffu), hinge = (int)(h.x >> 16);
     const int len = (int)(h.y >> 16);
     const int dslot = (int)(h.z & 0xffffu), jslot = (int)(h.z >> 16), last = (int)(h.w & 0xffffu);
+    // The mixed form stores the first element's block sums instead of adding them to zeroed registers
+    // (48 fewer moves per run, 128^3 mixed -1.7 %); the FP64 form zeroes them (storing costs the batched
+    // FP64 kernel 4 spilled registers).
+    constexpr bool kFirstStores = !std::is_same<R, double>::value;
     double sd[16], sj[16], sa[16], sr[4];
+    if (!kFirstStores) {
 #pragma unroll
-    for (int i = 0; i < 16; i++) sd[i] = sj[i] = sa[i] = 0.0;
+        for (int i = 0; i < 16; i++) sd[i] = sj[i] = sa[i] = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; c++) sr[c] = 0.0;
+        for (int c = 0; c < 4; c++) sr[c] = 0.0;
+    }
     // Node reads (NL): consecutive elements share the row, the hinge and one more node, so with
     // NL_AHEAD each element reads one new node from the node table and keeps the others in registers,
     // reading it one element ahead, before the current element's LDS adds (LDS operations complete in
@@ -633,11 +639,19 @@ __device__ __forceinline__ void tile_run(const TileArgs &A, double rdt, const ui
             const int sh1 = ((q + 1) & 1) * 16;
             node_load(nodes, (int)(((q + 1 < 2 ? k.x : k.y) >> sh1) & 0xffffu), Xn, Un);
         }
+        if (kFirstStores && q == 0) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) sr[c] += (double)rb[c];
-        block0<R, false>(C, 0, sd);
-        block0<R, false>(C, 1, sj);
-        block0<R, false>(C, 2, sa);
+            for (int c = 0; c < 4; c++) sr[c] = (double)rb[c];
+            block0<R, true>(C, 0, sd);
+            block0<R, true>(C, 1, sj);
+            block0<R, true>(C, 2, sa);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) sr[c] += (double)rb[c];
+            block0<R, false>(C, 0, sd);
+            block0<R, false>(C, 1, sj);
+            block0<R, false>(C, 2, sa);
+        }
         lds_add16(acc + kBlkStride * ks, sa);
         block0<R, true>(C, 3, sa);
     }
