@@ -6,15 +6,20 @@
 
 namespace nsa {
 
-// Streaming accesses (the nt bit): data read or written once per launch -- a tile's run records,
-// its block-image write-out -- so that it does not displace the node data that neighbouring tiles
-// read again from L2.
+// Streaming accesses (the nt bit): data read or written once per launch -- a tile's run or element
+// records, its block-image or row write-out -- so that it does not displace the node data that
+// neighbouring tiles read again from L2.
 typedef double stream_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned stream_u2 __attribute__((ext_vector_type(2)));
 typedef unsigned stream_u4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_stream(double2 *p, double2 v) {
     __builtin_nontemporal_store((stream_d2){v.x, v.y}, reinterpret_cast<stream_d2 *>(p));
 }
 __device__ __forceinline__ void store_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ uint2 load_stream2(const uint2 *p) {
+    const stream_u2 t = __builtin_nontemporal_load(reinterpret_cast<const stream_u2 *>(p));
+    return make_uint2(t.x, t.y);
+}
 __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
     const stream_u4 t = __builtin_nontemporal_load(reinterpret_cast<const stream_u4 *>(p));
     return make_uint4(t.x, t.y, t.z, t.w);

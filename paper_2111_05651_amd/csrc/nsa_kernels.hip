@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
     const int64_t p0 = A.tile_eptr[tile], p1 = A.tile_eptr[tile + 1];
     int64_t p = p0 + tid;
     uint2 cur = make_uint2(0u, 0u);
-    if (p < p1) cur = A.rec[p];
+    if (p < p1) cur = load_stream2(A.rec + p);
     // CACHED: the geometry of the next record is loaded while the current one is integrated, and the
     // element id of the one after it an iteration earlier still, so no load waits on another in the loop
     GeoRaw gc, gn;
@@ -1073,7 +1073,7 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
     while (p < p1) {
         const int64_t pn = p + NT;
         uint2 nxt = make_uint2(0u, 0u);
-        if (pn < p1) nxt = A.rec[pn];
+        if (pn < p1) nxt = load_stream2(A.rec + pn);
         uint2 en2 = make_uint2(0u, 0u);
         if (CACHED) {
             if (pn < p1) geo_load(A, en.x, gn);
@@ -1094,7 +1094,7 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
         double v = racc[kResStride * r + c];
         double *o = A.rhsid + 3 * (int64_t)r0 + i;
         if (A.accumulate) v += *o;
-        *o = v;
+        store_stream(o, v);
     }
     for (int i = tid; i < nrows; i += NT) {
         double t = racc[kResStride * i + 3], m = racc[kResStride * i + 4];
@@ -1102,8 +1102,8 @@ __global__ __launch_bounds__(NT, 2) void k_residual(ResArgs A) {
             t += A.dt_rho[r0 + i];
             m += A.mass_rho[r0 + i];
         }
-        A.dt_rho[r0 + i] = t;
-        A.mass_rho[r0 + i] = m;
+        store_stream(A.dt_rho + r0 + i, t);
+        store_stream(A.mass_rho + r0 + i, m);
     }
 }
 
