@@ -207,11 +207,30 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
         q1_element<R>(A, rdt, load_stream(rp), load_stream(rp + 1), load_stream(rp + 2), nodes, acc, racc);
     }
     __syncthreads();
+    // the tile's 9 nblk values are contiguous: written as 16-byte pairs, with one 8-byte value first
+    // when the range starts off 16-byte alignment and one last when a value is left over
     double *out = A.values + 9 * b0;
-    for (int i = tid; i < 9 * nblk; i += NT) {
-        double v = acc[i];
-        if (A.accumulate) v += out[i];
-        store_stream(out + i, v);
+    const int n = 9 * nblk;
+    const int lead = (int)((reinterpret_cast<uintptr_t>(out) >> 3) & 1);
+    const int npair = (n - lead) >> 1;
+    double2 *out2 = reinterpret_cast<double2 *>(out + lead);
+    for (int i = tid; i < npair; i += NT) {
+        const double *src = acc + lead + 2 * i;
+        double2 v = make_double2(src[0], src[1]);
+        if (A.accumulate) {
+            const double2 o = out2[i];
+            v.x += o.x;
+            v.y += o.y;
+        }
+        store_stream(out2 + i, v);
+    }
+    if (tid < 2) {
+        const int i = tid == 0 ? (lead ? 0 : -1) : (((n - lead) & 1) ? n - 1 : -1);
+        if (i >= 0) {
+            double v = acc[i];
+            if (A.accumulate) v += out[i];
+            store_stream(out + i, v);
+        }
     }
     double *rout = A.rhs + 3 * (int64_t)r0;
     for (int i = tid; i < 3 * nrows; i += NT) {
