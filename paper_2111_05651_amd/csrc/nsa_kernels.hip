@@ -675,11 +675,10 @@ __device__ __forceinline__ void run_tile(const TileArgs &A, int64_t tile, double
     // The node ids sit at a fixed stride per tile (padded with a node of the tile), so the first
     // kSpec passes of node gathers need no tile header: they are issued first and wait for one round
     // trip (ids, then coordinates and velocities) while the header loads are in flight; only their
-    // LDS stores depend on the tile's node count. Two passes cover the throughput plan's tiles (about
-    // 440 nodes at 128^3). The one-wavefront tiles hold at most ~140 nodes, yet four passes measured
-    // faster there than the three that cover them (128^3, 160-block tiles: mixed 1.60 -> 1.52 ms,
-    // FP64 1.59 -> 1.57 ms).
-    constexpr int kSpec = NT == 64 ? 4 : 2;
+    // LDS stores depend on the tile's node count. Two passes: they cover the throughput plan's tiles
+    // (about 440 nodes at 128^3), and in the one-wavefront 128-block tiles (about 115 nodes) two
+    // measured faster than three or four (128^3 FP64 1.527 / 1.537 / 1.544 ms).
+    constexpr int kSpec = 2;
     const int32_t *nid = A.tile_npad + tile * A.cap_nodes;
     int64_t gs[kSpec];
 #pragma unroll
