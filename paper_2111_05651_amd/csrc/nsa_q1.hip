@@ -168,6 +168,8 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
     const int64_t tile = xcd_item(blockIdx.x);  // XCD-aware order as in the tetrahedral kernel
     if (tile >= A.ntiles) return;
     const int tid = threadIdx.x;
+    // throughput plan: the prologue at raised wave priority, as in the tetrahedral kernel (2048^2: -1.7 %)
+    if constexpr (NT > 64) __builtin_amdgcn_s_setprio(2);
     const int r0 = A.tile_row[tile], nrows = A.tile_row[tile + 1] - r0;
     const int64_t b0 = A.tile_b0[tile];
     const int nblk = (int)(A.tile_b0[tile + 1] - b0);
@@ -201,6 +203,7 @@ __global__ __launch_bounds__(NT, q1_min_blocks<R>()) void k_q1(Q1Args A) {
     for (int i = tid; i < 9 * nblk; i += NT) acc[i] = 0.0;
     for (int i = tid; i < 3 * nrows; i += NT) racc[i] = 0.0;
     __syncthreads();
+    if constexpr (NT > 64) __builtin_amdgcn_s_setprio(0);
     const double rdt = A.rho / A.dt;
     for (int64_t p = p0 + tid; p < p1; p += NT) {
         const uint4 *rp = A.recs + 3 * p;
