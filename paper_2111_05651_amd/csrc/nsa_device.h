@@ -50,6 +50,20 @@ __device__ __forceinline__ double fast_rcp(double x) {
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Norm of the element's mean velocity for the stabilisation parameters, from its square x2: the
+// hardware reciprocal square root (about 23 correct bits) and one Newton step y += (r/2)(x2 - y^2),
+// which leaves a relative error of about 1.5 * 2^-46, against the 18 instructions of a correctly
+// rounded sqrt (range scaling, two iterations, two corrections, special-value select). Below 1e-300
+// (and for x2 = 0, where the estimate is infinite) the norm is taken as 0; it then only enters tau
+// beside rho/dt and is negligible there.
+__device__ __forceinline__ double tau_norm(double x2) {
+    const double r = __builtin_amdgcn_rsq(x2);
+    const double y = x2 * r;
+    const double y1 = fma(0.5 * r, fma(-y, y, x2), y);
+    return x2 > 1e-300 ? y1 : 0.0;
+}
+__device__ __forceinline__ float tau_norm(float x2) { return __builtin_amdgcn_sqrtf(x2); }
+
 // x^(-1/3) for x > 0: FP32 estimate (2^(-log2(x)/3), relative error a few 1e-6 over the range) refined
 // by two Newton steps r += r (1 - x r^3) / 3, each of which about squares the relative error (2e-6 ->
 // ~1e-11 -> below FP64 rounding).

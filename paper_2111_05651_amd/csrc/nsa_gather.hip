@@ -81,7 +81,7 @@ __device__ __forceinline__ void element_data(const int loc[4], const double *nod
     R su[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) su[c] = U[0][c] + U[1][c] + U[2][c] + U[3][c];
-    const R an = (R)0.25 * sqrt(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
+    const R an = (R)0.25 * tau_norm(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
     const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
     const R t2 = mu + (R)0.5 * rho * an * h;
 #pragma unroll

@@ -324,7 +324,7 @@ __device__ __forceinline__ void setup_t(const Geo2 &g, const double Ud[4][3], do
     const R rdt = (R)(rho_d / dt_d);
 #pragma unroll
     for (int c = 0; c < 3; c++) E.su[c] = E.U[0][c] + E.U[1][c] + E.U[2][c] + E.U[3][c];
-    const R an = (R)0.25 * sqrt(E.su[0] * E.su[0] + E.su[1] * E.su[1] + E.su[2] * E.su[2]);
+    const R an = (R)0.25 * tau_norm(E.su[0] * E.su[0] + E.su[1] * E.su[1] + E.su[2] * E.su[2]);
     const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
     const R t2 = mu + (R)0.5 * rho * an * h;
 #pragma unroll
@@ -461,7 +461,7 @@ __device__ __forceinline__ void row0_setup(const Geo2 &g, const double Ud[4][3],
     R su[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) su[c] = U[0][c] + U[1][c] + U[2][c] + U[3][c];
-    const R an = (R)0.25 * sqrt(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
+    const R an = (R)0.25 * tau_norm(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
     const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
     const R t2 = mu + (R)0.5 * rho * an * h;
     const R v4 = V * (R)0.25, v20 = V * (R)0.05, muV = mu * V, t2V = t2 * V, t1rho = t1 * rho;
