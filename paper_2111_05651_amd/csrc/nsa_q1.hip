@@ -88,10 +88,14 @@ __device__ __forceinline__ void q1_element(const Q1Args &A, double rdt_d, const 
         w[g] = (R)fabs(det);
         area += fabs(det);
     }
-    const double hd = sqrt(area);
-    const R h = (R)hd, rh = (R)(1.0 / hd), rho = (R)A.rho, mu = (R)A.mu, rdt = (R)rdt_d;
+    // h = area^(1/2) and 1/h from one reciprocal square root: the hardware estimate (about 23 correct
+    // bits) and one Newton step r (3 - area r^2) / 2 (relative error about 1.5 * 2^-46); the area of a
+    // valid element is positive and far inside the estimate's range
+    double rhd = __builtin_amdgcn_rsq(area);
+    rhd = rhd * fma(-0.5 * area, rhd * rhd, 1.5);
+    const R h = (R)(area * rhd), rh = (R)rhd, rho = (R)A.rho, mu = (R)A.mu, rdt = (R)rdt_d;
     R ab[2] = {(R)0.25 * (U[0][0] + U[1][0] + U[2][0] + U[3][0]), (R)0.25 * (U[0][1] + U[1][1] + U[2][1] + U[3][1])};
-    const R an = sqrt(ab[0] * ab[0] + ab[1] * ab[1]);
+    const R an = tau_norm(ab[0] * ab[0] + ab[1] * ab[1]);
     const R t1 = fast_rcp(rdt + (R)4 * mu * rh * rh + (R)2 * rho * an * rh);
     const R t2 = mu + (R)0.5 * rho * an * h;
     R ug[4][2], ag[4][4];  // velocity at g, a_g . grad N_a
