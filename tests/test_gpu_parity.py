@@ -89,6 +89,32 @@ def test_degenerate_parameters():
                 assert e <= tol_of(mode[0]), (rho, mu, dt, mode, err)
 
 
+
+def test_tiny_velocity_fp64():
+    """Velocities of order 1e-152: every element's squared velocity sum lies below 1e-300, where the
+    kernels take the velocity norm in tau as 0 (beside rho/dt it is far below FP64 resolution there)
+    while the oracle takes the exact norm. Catches a NaN or infinity from the reciprocal square root
+    of such a value. FP64 only: FP32 cannot represent these velocities."""
+    m = inputs.make_mesh(4, jitter=True, permute=True, velocity="vortex", seed=25)
+    vel = np.ascontiguousarray(m.velocity * 1e-152)
+    su = vel[m.lnods].sum(axis=1)
+    assert (su * su).sum(axis=1).max() < 1e-300 and np.abs(vel).max() > 1e-153
+    say(f"[tiny velocity] nelem={m.nelem}")
+    ref_v, ref_r = oracle.assemble(m, velocity=vel)
+    mesh = nsa.Mesh.from_inputs(m, tile_blocks_gather=320, tile_rows_residual=64).upload()
+    for scat in (nsa.ATOMIC, nsa.COLOUR):
+        for kern in (nsa.KERNEL_TILED, nsa.KERNEL_DIRECT, nsa.KERNEL_GATHER):
+            v, r = gpu_assemble(mesh, m, nsa.FP64, scat, kernel=kern, vel=vel)
+            assert np.isfinite(v).all() and np.isfinite(r).all()
+            assert_parity(v, ref_v, r, ref_r, TOL_FP64, f"tiny velocity {scat} {kern}")
+    ref = oracle.residual(m, velocity=vel)
+    outs = nsa.assemble_residual(mesh, torch.from_numpy(vel).cuda(), m.rho, m.mu, m.dt, precision=nsa.FP64)
+    torch.cuda.synchronize()
+    for name, g, r in zip(("rhsid", "dt_rho", "mass_rho"), outs, ref):
+        g = g.cpu().numpy()
+        assert np.isfinite(g).all(), name
+        assert np.abs(g - r).max() <= TOL_FP64 * np.abs(r).max(), name
+
 def test_accumulate():
     m = inputs.make_mesh(4, jitter=True, permute=True, seed=24)
     ref_v, ref_r = oracle.assemble(m)
